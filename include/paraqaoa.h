@@ -1,0 +1,192 @@
+/*
+ * paraqaoa.h -- C ABI of libparaqaoa, the MI355X (gfx950) hot path of
+ * ParaQAOA (arXiv 2603.26232): batched depth-p QAOA state-vector simulation
+ * of the subgraphs produced by the divide-and-conquer partition, the cut
+ * expectation, top-k bitstring extraction, integer cut evaluation of merged
+ * full-graph assignments and the merge itself.
+ *
+ * Conventions (all entry points):
+ *   - A subgraph with n vertices is simulated on n qubits; amplitude index z
+ *     has bit j = local vertex j (local order = increasing global index), and
+ *     bit value 1 puts the vertex in S (the bitstring picture of Sec. 2.4).
+ *   - H_C = diag(C(z)) with C(z) = sum over edges of w_uv [z_u != z_v] (the
+ *     Max-Cut objective of Sec. 2.1); H_M = sum_j X_j; U_C = e^{-i gamma H_C},
+ *     U_M = e^{-i beta H_M}; |psi> = U_M(b_p)U_C(g_p)...U_M(b_1)U_C(g_1)|+>^n
+ *     (the QAOA ansatz of Sec. 2.2).
+ *   - Angles, <C> and gradients are IEEE double; amplitudes are complex64
+ *     on the device; cut values are int64.
+ *   - Pointers named d_* are device pointers (HBM); h_* / plain pointers
+ *     named in "host" comments are host pointers. The caller owns every
+ *     buffer, device and host; the library never frees caller memory.
+ *   - Every call that takes a stream only enqueues work on it and never
+ *     synchronises the device, except qaoa_batch_create and
+ *     qaoa_merge_beam, which copy host arrays to the device and wait for
+ *     that copy. Outputs are valid once the caller synchronises the stream.
+ *     A handle must not be used by two host threads at once.
+ *   - Errors are reported as status codes only; nothing aborts or throws.
+ *     All arguments are checked before any work is enqueued; on an error
+ *     no work is enqueued and qaoa_last_error() holds a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - For identical inputs on the same device and build, every output is
+ *     bit-identical (fixed-order reductions, no floating-point atomics).
+ */
+#ifndef PARAQAOA_H
+#define PARAQAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QAOA_OK = 0,
+    QAOA_ERR_INVALID_ARG = 1,          /* NULL where a pointer is required, bad id, ... */
+    QAOA_ERR_OUT_OF_RANGE = 2,         /* n > 30, p > 32, k > 64, W too large, ... */
+    QAOA_ERR_WORKSPACE_TOO_SMALL = 3,  /* workspace smaller than *_workspace_bytes */
+    QAOA_ERR_HIP = 4,                  /* a HIP runtime call failed (text in last_error) */
+    QAOA_ERR_STATE = 5,                /* call order violated (e.g. top-k before apply) */
+    QAOA_ERR_NOT_SUPPORTED = 6         /* e.g. a subgraph's weight sum above 2047 */
+} qaoa_status_t;
+
+/* Opaque handle: host metadata plus views into the caller's workspace. */
+typedef struct qaoa_batch_s* qaoa_batch_t;
+
+/* A hipStream_t passed as an untyped pointer; NULL means the null stream. */
+typedef void* qaoa_stream_t;
+
+#define QAOA_MAX_QUBITS 30
+#define QAOA_MAX_DEPTH 32
+#define QAOA_MAX_K 64
+#define QAOA_MAX_WEIGHT_SUM 2047 /* per subgraph: sum of its edge weights */
+#define QAOA_MAX_BEAM 8192
+
+/* create flags */
+#define QAOA_FLAG_GRADIENT 0x1u /* reserve the adjoint state; enables qaoa_expectation_grad */
+#define QAOA_FLAG_TOPK_RAW 0x2u /* top-k over all z; default: only z with bit 0 clear */
+
+/* Workspace size for a batch (paper Sec. 3.3: the subgraphs {G[V_i]} that
+ * Alg. 1 produces, each solved by its own QAOA instance).
+ *   B              number of subgraphs (>= 1)
+ *   num_qubits     host [B], each in 1..30
+ *   edge_offsets   host [B+1], subgraph b owns edges [off[b], off[b+1])
+ *   edge_w         host [off[B]] edge weights (>= 0), or NULL for unit weights
+ *   max_p          largest depth that will be applied (1..32)
+ *   max_k          largest k that qaoa_topk will be asked for (1..64)
+ *   flags          QAOA_FLAG_*
+ *   out_bytes      receives the byte count (the workspace must be 256-byte aligned) */
+qaoa_status_t qaoa_workspace_bytes(int32_t B, const int32_t* num_qubits, const int64_t* edge_offsets,
+                                   const int32_t* edge_w, int32_t max_p, int32_t max_k, uint32_t flags,
+                                   size_t* out_bytes);
+
+/* Build a batch: validates the subgraphs, lays out states, cut tables, phase
+ * tables and partial sums in the caller's workspace, copies the edge lists to
+ * the device and builds every subgraph's integer cut table C(z) (uint16).
+ *   edge_u, edge_v host [off[B]] local vertex ids in [0, n_b), u != v
+ *   edge_w         host weights >= 0 or NULL (unit); per-subgraph sum <= 2047
+ *   d_workspace    device buffer of at least qaoa_workspace_bytes bytes,
+ *                  256-byte aligned; it must outlive the handle
+ *   stream         the copy and the table build run on it; the call waits for
+ *                  the host-to-device copy before returning
+ *   out            receives the handle (free it with qaoa_batch_destroy) */
+qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits, const int64_t* edge_offsets,
+                                const int32_t* edge_u, const int32_t* edge_v, const int32_t* edge_w,
+                                int32_t max_p, int32_t max_k, uint32_t flags, void* d_workspace,
+                                size_t workspace_bytes, qaoa_stream_t stream, qaoa_batch_t* out);
+
+/* Free the host metadata of a handle. NULL is accepted. Caller memory is
+ * untouched; pending work on the handle's workspace must have finished. */
+qaoa_status_t qaoa_batch_destroy(qaoa_batch_t h);
+
+/* The QAOA ansatz (Sec. 2.2): reset every subgraph's state to |+>^n and apply
+ * p layers U_M(beta_l) U_C(gamma_l), l = 1..p.
+ *   p          1..max_p
+ *   d_gamma    device double [B*p], row-major (subgraph b, layer l)
+ *   d_beta     device double [B*p], same layout
+ * Also leaves the per-tile partial sums of <C> for qaoa_expectation. */
+qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const double* d_gamma, const double* d_beta,
+                                qaoa_stream_t stream);
+
+/* The QAOA objective <psi|H_C|psi> = sum_z |psi(z)|^2 C(z) (Sec. 2.2) of the
+ * state left by the last qaoa_apply_layers (or qaoa_expectation_grad).
+ *   d_out      device double [B]
+ * QAOA_ERR_STATE if neither has run since creation. */
+qaoa_status_t qaoa_expectation(qaoa_batch_t h, double* d_out, qaoa_stream_t stream);
+
+/* Selective Distribution Exploration (Sec. 3.3.2): for every subgraph the k
+ * bitstrings with the largest probability pi(z) = |psi(z)|^2 of the state
+ * left by the last qaoa_apply_layers, ordered by pi descending, ties by z
+ * ascending. Default mode considers only z with bit 0 clear (pi(z) =
+ * pi(~z) exactly, so this keeps one member of each complement pair and the
+ * merge adds the complements); QAOA_FLAG_TOPK_RAW considers all z.
+ *   k          1..max_k
+ *   d_idx      device uint32 [B*k]; rows with fewer candidates than k are
+ *              padded with 0xFFFFFFFF
+ *   d_prob     device float [B*k]; padding rows hold -1
+ * QAOA_ERR_STATE unless qaoa_apply_layers ran after the last
+ * qaoa_expectation_grad (which consumes the state). */
+qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, float* d_prob, qaoa_stream_t stream);
+
+/* Exact gradient of every subgraph's <C> with respect to its angles, by the
+ * adjoint sweep (derivative of e^{-i theta H} is -i H e^{-i theta H}), for the
+ * angle optimisation that Sec. 2.2 describes. Needs QAOA_FLAG_GRADIENT.
+ *   d_gamma, d_beta   device double [B*p] (as in qaoa_apply_layers)
+ *   d_E               device double [B]   receives <C>
+ *   d_dgamma, d_dbeta device double [B*p] receive dE/dgamma, dE/dbeta
+ * The state is consumed (call qaoa_apply_layers before qaoa_topk). */
+qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const double* d_gamma, const double* d_beta,
+                                    double* d_E, double* d_dgamma, double* d_dbeta, qaoa_stream_t stream);
+
+/* One Adam step (Kingma and Ba 2015) in FP64 on a flat parameter vector,
+ * used for the angle optimisation of Sec. 2.2 (maximise = 1) and for the
+ * angle-predictor's training (maximise = 0).
+ *   count      number of parameters (>= 1)
+ *   d_theta    device double [count], updated in place
+ *   d_grad     device double [count]
+ *   d_m, d_v   device double [count], moment estimates (start at zero)
+ *   d_step     device int32 [1], steps taken so far; incremented by the call
+ *   lr, beta1, beta2, eps  the usual Adam constants */
+qaoa_status_t qaoa_adam_step(int32_t count, double* d_theta, const double* d_grad, double* d_m, double* d_v,
+                             int32_t* d_step, double lr, double beta1, double beta2, double eps,
+                             int32_t maximise, qaoa_stream_t stream);
+
+/* CutVal (Sec. 2.1) of num_assign full-graph assignments, as the merge of
+ * Alg. 2 evaluates each concatenated bitstring over all edges of G.
+ *   d_u, d_v   device int32 [num_edges] vertex ids
+ *   d_w        device int32 [num_edges] weights, or NULL for unit weights
+ *   d_assign   device uint32 [num_assign][ceil(num_vertices/32)], vertex t is
+ *              word t/32, bit t%32
+ *   d_cut      device int64 [num_assign]; -1 if any edge id lies outside
+ *              [0, num_vertices) */
+qaoa_status_t maxcut_eval(int32_t num_vertices, int64_t num_edges, const int32_t* d_u, const int32_t* d_v,
+                          const int32_t* d_w, int64_t num_assign, const uint32_t* d_assign, int64_t* d_cut,
+                          qaoa_stream_t stream);
+
+/* Where subgraph b's state lives: the byte offset, inside the workspace, of
+ * its 2^n complex64 amplitudes (interleaved real, imaginary; index z). After
+ * qaoa_apply_layers they hold |psi>; after qaoa_expectation_grad they hold
+ * an intermediate of the adjoint sweep. For inspection and tests. */
+qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* out_offset);
+
+/* Text of a status code (static storage). */
+const char* qaoa_status_string(qaoa_status_t s);
+
+/* Detail of the last error on this thread ("" if none). */
+const char* qaoa_last_error(void);
+
+/* Kernel timing for measurement: while enabled, the library brackets every
+ * launch of its kernels with HIP events on the launch stream.
+ * qaoa_profile_read waits for those events and returns, for the named
+ * kernel ("fwd_pass", "bwd_pass", "small", "cut_tables", "angle_prep",
+ * "reduce", "topk", "maxcut", "adam", "merge_expand", "merge_select"), the
+ * number of launches and their summed duration in milliseconds since the
+ * last qaoa_profile_enable(1). Not for use while another thread launches. */
+qaoa_status_t qaoa_profile_enable(int32_t on);
+qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARAQAOA_H */

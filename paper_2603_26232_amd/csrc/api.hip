@@ -1,0 +1,585 @@
+// C ABI of libparaqaoa (declared in include/paraqaoa.h): argument checks,
+// workspace layout, host-side pass programs and kernel launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/paraqaoa.h"
+#include "common.h"
+
+using namespace pq;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512] = "";
+
+static qaoa_status_t fail(qaoa_status_t s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static qaoa_status_t fail(qaoa_status_t s, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+static qaoa_status_t ok()
+{
+    g_err[0] = 0;
+    return QAOA_OK;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(QAOA_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// kernel timing (measurement hook)
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    hipEvent_t a, b;
+};
+struct Profiler {
+    bool on = false;
+    std::map<std::string, std::vector<ProfRec>> recs;
+    std::vector<ProfRec> pool;
+};
+Profiler g_prof;
+
+struct ProfScope {
+    const char* name;
+    hipStream_t s;
+    ProfRec r{};
+    bool active;
+    ProfScope(const char* n, hipStream_t st) : name(n), s(st), active(g_prof.on)
+    {
+        if (!active) return;
+        if (!g_prof.pool.empty()) {
+            r = g_prof.pool.back();
+            g_prof.pool.pop_back();
+        } else {
+            (void)hipEventCreate(&r.a);
+            (void)hipEventCreate(&r.b);
+        }
+        (void)hipEventRecord(r.a, s);
+    }
+    ~ProfScope()
+    {
+        if (!active) return;
+        (void)hipEventRecord(r.b, s);
+        g_prof.recs[name].push_back(r);
+    }
+};
+}  // namespace
+
+extern "C" qaoa_status_t qaoa_profile_enable(int32_t on)
+{
+    for (auto& kv : g_prof.recs)
+        for (auto& r : kv.second) {
+            (void)hipEventSynchronize(r.b);
+            g_prof.pool.push_back(r);
+        }
+    g_prof.recs.clear();
+    g_prof.on = on != 0;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms)
+{
+    if (!kernel || !launches || !total_ms) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
+    *launches = 0;
+    *total_ms = 0.0;
+    auto it = g_prof.recs.find(kernel);
+    if (it == g_prof.recs.end()) return ok();
+    for (auto& r : it->second) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        *total_ms += ms;
+        *launches += 1;
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Plan {
+    int32_t B = 0, max_p = 0, max_k = 0;
+    uint32_t flags = 0;
+    std::vector<SubDesc> subs;
+    int32_t total_tiles = 0;
+    int64_t total_edges = 0;
+    int lut_max = 1;
+    // region offsets
+    uint64_t o_subs = 0, o_work_all = 0, o_work_cls[MAX_GROUPS + 1] = {}, o_small = 0, o_edges = 0,
+             o_coef = 0, o_lut = 0, o_pe = 0, o_pgb = 0, o_pgg = 0, o_keys = 0, total = 0;
+    int nwork_cls[MAX_GROUPS + 1] = {};
+    int nsmall = 0;
+    // host images of the metadata regions
+    std::vector<int2> work_all, work_cls[MAX_GROUPS + 1];
+    std::vector<int32_t> small;
+};
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+int groups_for(int n)
+{
+    if (n <= SMALL_MAX_N) return 1;
+    const int rest = n - TILE_BITS;
+    return 1 + (rest + B_GROUP_MAX - 1) / B_GROUP_MAX;
+}
+
+qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const int32_t* ew, int32_t max_p,
+                        int32_t max_k, uint32_t flags, Plan& P)
+{
+    if (B < 1) return fail(QAOA_ERR_INVALID_ARG, "B = %d must be >= 1", B);
+    if (!nq || !eoff) return fail(QAOA_ERR_INVALID_ARG, "num_qubits and edge_offsets are required");
+    if (max_p < 1 || max_p > MAX_P) return fail(QAOA_ERR_OUT_OF_RANGE, "max_p = %d outside 1..%d", max_p, MAX_P);
+    if (max_k < 1 || max_k > MAX_K) return fail(QAOA_ERR_OUT_OF_RANGE, "max_k = %d outside 1..%d", max_k, MAX_K);
+    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW))
+        return fail(QAOA_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if (eoff[0] != 0) return fail(QAOA_ERR_INVALID_ARG, "edge_offsets[0] = %lld must be 0", (long long)eoff[0]);
+    P.B = B;
+    P.max_p = max_p;
+    P.max_k = max_k;
+    P.flags = flags;
+    P.subs.assign(B, SubDesc{});
+    const bool grad = flags & QAOA_FLAG_GRADIENT;
+    int64_t tiles = 0;
+    for (int b = 0; b < B; ++b) {
+        const int n = nq[b];
+        if (n < 1 || n > QAOA_MAX_QUBITS)
+            return fail(QAOA_ERR_OUT_OF_RANGE, "subgraph %d has %d qubits (1..%d)", b, n, QAOA_MAX_QUBITS);
+        if (eoff[b + 1] < eoff[b])
+            return fail(QAOA_ERR_INVALID_ARG, "edge_offsets not monotone at %d", b);
+        int64_t wsum = 0;
+        for (int64_t e = eoff[b]; e < eoff[b + 1]; ++e) {
+            const int64_t w = ew ? ew[e] : 1;
+            if (w < 0) return fail(QAOA_ERR_INVALID_ARG, "edge %lld has negative weight", (long long)e);
+            wsum += w;
+        }
+        if (wsum > QAOA_MAX_WEIGHT_SUM)
+            return fail(QAOA_ERR_NOT_SUPPORTED, "subgraph %d weight sum %lld exceeds %d", b, (long long)wsum,
+                        QAOA_MAX_WEIGHT_SUM);
+        SubDesc& d = P.subs[b];
+        d.n = n;
+        d.ngroups = groups_for(n);
+        d.gstart[0] = 0;
+        d.gsize[0] = n < TILE_BITS ? n : TILE_BITS;
+        if (d.ngroups > 1) {
+            const int rest = n - TILE_BITS, G1 = d.ngroups - 1;
+            int q = TILE_BITS;
+            for (int g = 1; g <= G1; ++g) {
+                const int sz = rest / G1 + (g <= rest % G1 ? 1 : 0);
+                d.gstart[g] = q;
+                d.gsize[g] = sz;
+                q += sz;
+            }
+        }
+        d.lut_len = (int32_t)wsum + 1;
+        d.ntiles = n > TILE_BITS ? (1 << (n - TILE_BITS)) : 1;
+        d.tile_base = (int32_t)tiles;
+        d.nedges = (int32_t)(eoff[b + 1] - eoff[b]);
+        tiles += d.ntiles;
+        if (d.lut_len > P.lut_max) P.lut_max = d.lut_len;
+    }
+    if (tiles > (1ll << 30)) return fail(QAOA_ERR_OUT_OF_RANGE, "batch too large (%lld tiles)", (long long)tiles);
+    P.total_tiles = (int32_t)tiles;
+    P.total_edges = eoff[B];
+
+    // work lists: every tile (tables, top-k); per group-count class (passes)
+    P.work_all.reserve(tiles);
+    for (int b = 0; b < B; ++b)
+        for (int t = 0; t < P.subs[b].ntiles; ++t) P.work_all.push_back(make_int2(b, t));
+    for (int G = 2; G <= MAX_GROUPS; ++G) {
+        // larger subgraphs first
+        std::vector<int> order;
+        for (int b = 0; b < B; ++b)
+            if (P.subs[b].ngroups == G) order.push_back(b);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return P.subs[a].n > P.subs[c].n; });
+        for (int b : order)
+            for (int t = 0; t < P.subs[b].ntiles; ++t) P.work_cls[G].push_back(make_int2(b, t));
+        P.nwork_cls[G] = (int)P.work_cls[G].size();
+    }
+    for (int b = 0; b < B; ++b)
+        if (P.subs[b].ngroups == 1) P.small.push_back(b);
+    P.nsmall = (int)P.small.size();
+
+    // regions
+    uint64_t o = 0;
+    auto region = [&](uint64_t bytes, uint64_t align) {
+        o = align_up(o, align);
+        const uint64_t r = o;
+        o += bytes;
+        return r;
+    };
+    P.o_subs = region(sizeof(SubDesc) * B, 256);
+    P.o_work_all = region(sizeof(int2) * tiles, 256);
+    for (int G = 2; G <= MAX_GROUPS; ++G) P.o_work_cls[G] = region(sizeof(int2) * P.nwork_cls[G], 256);
+    P.o_small = region(sizeof(int32_t) * (P.nsmall + 1), 256);
+    P.o_edges = region(sizeof(int32_t) * 3 * (P.total_edges + 1), 256);
+    P.o_coef = region(sizeof(float2) * B * max_p, 256);
+    uint64_t lut_total = 0;
+    for (int b = 0; b < B; ++b) lut_total += (uint64_t)max_p * P.subs[b].lut_len;
+    P.o_lut = region(sizeof(float2) * lut_total, 256);
+    P.o_pe = region(sizeof(double) * tiles, 256);
+    P.o_pgb = region(grad ? sizeof(double) * tiles * max_p * MAX_GROUPS : 0, 256);
+    P.o_pgg = region(grad ? sizeof(double) * tiles * max_p : 0, 256);
+    P.o_keys = region(sizeof(uint64_t) * tiles * max_k, 256);
+    uint64_t lut_o = P.o_lut, eo = P.o_edges;
+    for (int b = 0; b < B; ++b) {
+        SubDesc& d = P.subs[b];
+        const uint64_t dim = 1ull << d.n;
+        d.coef = P.o_coef + sizeof(float2) * (uint64_t)b * max_p;
+        d.lut = lut_o;
+        lut_o += sizeof(float2) * (uint64_t)max_p * d.lut_len;
+        d.edges = eo + sizeof(int32_t) * 3 * (uint64_t)eoff[b];
+        d.psi = region(dim * sizeof(float2), 4096);
+        d.lam = grad ? region(dim * sizeof(float2), 4096) : 0;
+        d.tab = region(dim * sizeof(uint16_t), 4096);
+        d.tabB = d.ngroups >= 2 ? region(dim * sizeof(uint16_t), 4096) : 0;
+    }
+    (void)eo;
+    P.total = align_up(o, 4096);
+    return ok();
+}
+
+// Serpentine pass program for a subgraph class with G >= 2 qubit groups.
+struct Op {
+    bool phase;
+    int g, l;
+};
+
+std::vector<Op> forward_ops(int G, int p)
+{
+    std::vector<Op> ops;
+    for (int l = 0; l < p; ++l) {
+        ops.push_back({true, -1, l});
+        for (int i = 0; i < G; ++i) ops.push_back({false, (l % 2 == 0) ? i : G - 1 - i, l});
+    }
+    return ops;
+}
+
+std::vector<PassOps> group_passes(const std::vector<Op>& ops)
+{
+    std::vector<PassOps> out;
+    PassOps cur{};
+    bool have = false;
+    int pending = -1;
+    for (const Op& op : ops) {
+        if (op.phase) {
+            pending = op.l;
+            continue;
+        }
+        if (have && cur.group == op.g && cur.ph < 0 && cur.post < 0) {
+            cur.ph = pending;
+            cur.post = op.l;
+            pending = -1;
+            continue;
+        }
+        if (have) out.push_back(cur);
+        cur = PassOps{};
+        cur.group = op.g;
+        cur.pre = pending < 0 ? op.l : -1;
+        cur.ph = pending;
+        cur.post = pending < 0 ? -1 : op.l;
+        pending = -1;
+        have = true;
+    }
+    if (have) {
+        if (pending >= 0) cur.ph = pending;  // trailing phase of a reversed program
+        out.push_back(cur);
+    }
+    return out;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct qaoa_batch_s {
+    Plan P;
+    uint8_t* ws = nullptr;
+    SubDesc* d_subs = nullptr;
+    Partials part{};
+    bool state_valid = false;  // psi holds the ansatz state of the last apply
+    bool e_valid = false;      // <C> partials are fresh
+};
+
+extern "C" const char* qaoa_status_string(qaoa_status_t s)
+{
+    switch (s) {
+    case QAOA_OK: return "ok";
+    case QAOA_ERR_INVALID_ARG: return "invalid argument";
+    case QAOA_ERR_OUT_OF_RANGE: return "argument out of range";
+    case QAOA_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case QAOA_ERR_HIP: return "HIP runtime error";
+    case QAOA_ERR_STATE: return "call order violated";
+    case QAOA_ERR_NOT_SUPPORTED: return "not supported";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* qaoa_last_error(void) { return g_err; }
+
+extern "C" qaoa_status_t qaoa_workspace_bytes(int32_t B, const int32_t* num_qubits, const int64_t* edge_offsets,
+                                              const int32_t* edge_w, int32_t max_p, int32_t max_k,
+                                              uint32_t flags, size_t* out_bytes)
+{
+    if (!out_bytes) return fail(QAOA_ERR_INVALID_ARG, "out_bytes is NULL");
+    Plan P;
+    qaoa_status_t s = make_plan(B, num_qubits, edge_offsets, edge_w, max_p, max_k, flags, P);
+    if (s != QAOA_OK) return s;
+    *out_bytes = (size_t)P.total;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits, const int64_t* edge_offsets,
+                                           const int32_t* edge_u, const int32_t* edge_v, const int32_t* edge_w,
+                                           int32_t max_p, int32_t max_k, uint32_t flags, void* d_workspace,
+                                           size_t workspace_bytes, qaoa_stream_t stream, qaoa_batch_t* out)
+{
+    if (!out) return fail(QAOA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    Plan P;
+    qaoa_status_t s = make_plan(B, num_qubits, edge_offsets, edge_w, max_p, max_k, flags, P);
+    if (s != QAOA_OK) return s;
+    if (P.total_edges > 0 && (!edge_u || !edge_v)) return fail(QAOA_ERR_INVALID_ARG, "edge_u/edge_v are NULL");
+    for (int b = 0; b < B; ++b) {
+        const int n = P.subs[b].n;
+        for (int64_t e = edge_offsets[b]; e < edge_offsets[b + 1]; ++e) {
+            const int32_t u = edge_u[e], v = edge_v[e];
+            if (u < 0 || v < 0 || u >= n || v >= n || u == v)
+                return fail(QAOA_ERR_INVALID_ARG, "subgraph %d edge %lld = (%d, %d) invalid for n = %d", b,
+                            (long long)e, u, v, n);
+        }
+    }
+    if (!d_workspace) return fail(QAOA_ERR_INVALID_ARG, "d_workspace is NULL");
+    if (((uintptr_t)d_workspace) % 256) return fail(QAOA_ERR_INVALID_ARG, "d_workspace not 256-byte aligned");
+    if (workspace_bytes < P.total)
+        return fail(QAOA_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %llu", workspace_bytes,
+                    (unsigned long long)P.total);
+
+    // metadata image: [subs | work_all | work classes | small | edges]
+    const uint64_t meta_end = P.o_coef;
+    std::vector<uint8_t> img(meta_end, 0);
+    memcpy(img.data() + P.o_subs, P.subs.data(), sizeof(SubDesc) * B);
+    memcpy(img.data() + P.o_work_all, P.work_all.data(), sizeof(int2) * P.work_all.size());
+    for (int G = 2; G <= MAX_GROUPS; ++G)
+        if (P.nwork_cls[G]) memcpy(img.data() + P.o_work_cls[G], P.work_cls[G].data(), sizeof(int2) * P.nwork_cls[G]);
+    if (P.nsmall) memcpy(img.data() + P.o_small, P.small.data(), sizeof(int32_t) * P.nsmall);
+    int32_t* E = (int32_t*)(img.data() + P.o_edges);
+    for (int64_t e = 0; e < P.total_edges; ++e) {
+        E[3 * e] = edge_u[e];
+        E[3 * e + 1] = edge_v[e];
+        E[3 * e + 2] = edge_w ? edge_w[e] : 1;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)d_workspace;
+    void* pinned = nullptr;
+    HIP_TRY(hipHostMalloc(&pinned, meta_end, hipHostMallocDefault));
+    memcpy(pinned, img.data(), meta_end);
+    hipError_t e1 = hipMemcpyAsync(ws, pinned, meta_end, hipMemcpyHostToDevice, st);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(st) : e1;
+    (void)hipHostFree(pinned);
+    if (e2 != hipSuccess) return fail(QAOA_ERR_HIP, "metadata upload: %s", hipGetErrorString(e2));
+
+    qaoa_batch_s* h = new qaoa_batch_s();
+    h->P = std::move(P);
+    h->ws = ws;
+    h->d_subs = (SubDesc*)(ws + h->P.o_subs);
+    h->part.e = (double*)(ws + h->P.o_pe);
+    h->part.gb = (double*)(ws + h->P.o_pgb);
+    h->part.gg = (double*)(ws + h->P.o_pgg);
+    h->part.total_tiles = h->P.total_tiles;
+    {
+        ProfScope ps("cut_tables", st);
+        hipError_t e = launch_cut_tables(ws, h->d_subs, (const int2*)(ws + h->P.o_work_all), h->P.total_tiles, st);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(QAOA_ERR_HIP, "cut table kernel: %s", hipGetErrorString(e));
+        }
+    }
+    *out = h;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_batch_destroy(qaoa_batch_t h)
+{
+    delete h;
+    return ok();
+}
+
+static qaoa_status_t check_angles(qaoa_batch_t h, int32_t p, const double* g, const double* b)
+{
+    if (!h) return fail(QAOA_ERR_INVALID_ARG, "handle is NULL");
+    if (p < 1 || p > h->P.max_p) return fail(QAOA_ERR_OUT_OF_RANGE, "p = %d outside 1..%d", p, h->P.max_p);
+    if (!g || !b) return fail(QAOA_ERR_INVALID_ARG, "d_gamma/d_beta are NULL");
+    return QAOA_OK;
+}
+
+extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const double* d_gamma, const double* d_beta,
+                                           qaoa_stream_t stream)
+{
+    qaoa_status_t s = check_angles(h, p, d_gamma, d_beta);
+    if (s != QAOA_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Plan& P = h->P;
+    {
+        ProfScope ps("angle_prep", st);
+        HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
+    }
+    if (P.nsmall) {
+        ProfScope ps("small", st);
+        HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 0, h->part,
+                             P.lut_max, st));
+    }
+    for (int G = 2; G <= MAX_GROUPS; ++G) {
+        if (!P.nwork_cls[G]) continue;
+        std::vector<PassOps> passes = group_passes(forward_ops(G, p));
+        for (size_t i = 0; i < passes.size(); ++i) {
+            PassOps o = passes[i];
+            o.init = i == 0;
+            o.epi_e = i + 1 == passes.size();
+            ProfScope ps("fwd_pass", st);
+            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_cls[G]), P.nwork_cls[G], o,
+                                    h->part, P.lut_max, st));
+        }
+    }
+    h->state_valid = true;
+    h->e_valid = true;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_expectation(qaoa_batch_t h, double* d_out, qaoa_stream_t stream)
+{
+    if (!h) return fail(QAOA_ERR_INVALID_ARG, "handle is NULL");
+    if (!d_out) return fail(QAOA_ERR_INVALID_ARG, "d_out is NULL");
+    if (!h->e_valid) return fail(QAOA_ERR_STATE, "no state: call qaoa_apply_layers first");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("reduce", st);
+    HIP_TRY(launch_reduce(h->d_subs, h->P.B, 1, 0, h->part, d_out, nullptr, nullptr, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, float* d_prob, qaoa_stream_t stream)
+{
+    if (!h) return fail(QAOA_ERR_INVALID_ARG, "handle is NULL");
+    if (k < 1 || k > h->P.max_k) return fail(QAOA_ERR_OUT_OF_RANGE, "k = %d outside 1..%d", k, h->P.max_k);
+    if (!d_idx || !d_prob) return fail(QAOA_ERR_INVALID_ARG, "d_idx/d_prob are NULL");
+    if (!h->state_valid) return fail(QAOA_ERR_STATE, "no ansatz state: call qaoa_apply_layers first");
+    hipStream_t st = (hipStream_t)stream;
+    const Plan& P = h->P;
+    ProfScope ps("topk", st);
+    HIP_TRY(launch_topk(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_all), P.total_tiles, P.B, k,
+                        (P.flags & QAOA_FLAG_TOPK_RAW) ? 0 : 1, (uint64_t*)(h->ws + P.o_keys), nullptr, d_idx,
+                        d_prob, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const double* d_gamma,
+                                               const double* d_beta, double* d_E, double* d_dgamma,
+                                               double* d_dbeta, qaoa_stream_t stream)
+{
+    qaoa_status_t s = check_angles(h, p, d_gamma, d_beta);
+    if (s != QAOA_OK) return s;
+    if (!(h->P.flags & QAOA_FLAG_GRADIENT))
+        return fail(QAOA_ERR_STATE, "batch was created without QAOA_FLAG_GRADIENT");
+    if (!d_E || !d_dgamma || !d_dbeta) return fail(QAOA_ERR_INVALID_ARG, "output pointers are NULL");
+    hipStream_t st = (hipStream_t)stream;
+    Plan& P = h->P;
+    {
+        ProfScope ps("angle_prep", st);
+        HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
+    }
+    if (P.nsmall) {
+        ProfScope ps("small", st);
+        HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 1, h->part,
+                             P.lut_max, st));
+    }
+    for (int G = 2; G <= MAX_GROUPS; ++G) {
+        if (!P.nwork_cls[G]) continue;
+        const int2* work = (const int2*)(h->ws + P.o_work_cls[G]);
+        const int nw = P.nwork_cls[G];
+        std::vector<Op> ops = forward_ops(G, p);
+        std::vector<PassOps> fwd = group_passes(ops);
+        for (size_t i = 0; i + 1 < fwd.size(); ++i) {
+            PassOps o = fwd[i];
+            o.init = i == 0;
+            ProfScope ps("fwd_pass", st);
+            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, o, h->part, P.lut_max, st));
+        }
+        std::vector<Op> rev(ops.rbegin(), ops.rend());
+        std::vector<PassOps> bwd = group_passes(rev);
+        // the last forward pass (RX of the last group, layer p-1) and the
+        // first backward pass (its inverse) share one kernel
+        PassOps f = fwd.back();
+        f.fused = 1;
+        {
+            ProfScope ps("bwd_pass", st);
+            HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, f, h->part, P.lut_max, st));
+        }
+        for (size_t i = 1; i < bwd.size(); ++i) {
+            PassOps o = bwd[i];
+            o.last = i + 1 == bwd.size();
+            ProfScope ps("bwd_pass", st);
+            HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, o, h->part, P.lut_max, st));
+        }
+    }
+    {
+        ProfScope ps("reduce", st);
+        HIP_TRY(launch_reduce(h->d_subs, P.B, p, 1, h->part, d_E, d_dgamma, d_dbeta, st));
+    }
+    h->state_valid = false;
+    h->e_valid = true;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_adam_step(int32_t count, double* d_theta, const double* d_grad, double* d_m,
+                                        double* d_v, int32_t* d_step, double lr, double beta1, double beta2,
+                                        double eps, int32_t maximise, qaoa_stream_t stream)
+{
+    if (count < 1) return fail(QAOA_ERR_INVALID_ARG, "count = %d must be >= 1", count);
+    if (!d_theta || !d_grad || !d_m || !d_v || !d_step) return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && lr >= 0.0))
+        return fail(QAOA_ERR_OUT_OF_RANGE, "Adam constants out of range");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("adam", st);
+    HIP_TRY(launch_adam(count, d_theta, d_grad, d_m, d_v, d_step, lr, beta1, beta2, eps, maximise ? 1.0 : -1.0, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t maxcut_eval(int32_t num_vertices, int64_t num_edges, const int32_t* d_u,
+                                     const int32_t* d_v, const int32_t* d_w, int64_t num_assign,
+                                     const uint32_t* d_assign, int64_t* d_cut, qaoa_stream_t stream)
+{
+    if (num_vertices < 1) return fail(QAOA_ERR_INVALID_ARG, "num_vertices = %d", num_vertices);
+    if (num_edges < 0 || num_assign < 0) return fail(QAOA_ERR_INVALID_ARG, "negative count");
+    if (num_edges > 0 && (!d_u || !d_v)) return fail(QAOA_ERR_INVALID_ARG, "d_u/d_v are NULL");
+    if (num_assign > 0 && (!d_assign || !d_cut)) return fail(QAOA_ERR_INVALID_ARG, "d_assign/d_cut are NULL");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("maxcut", st);
+    HIP_TRY(launch_maxcut_eval(num_vertices, num_edges, d_u, d_v, d_w, num_assign, d_assign, d_cut, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* out_offset)
+{
+    if (!h || !out_offset) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
+    if (b < 0 || b >= h->P.B) return fail(QAOA_ERR_OUT_OF_RANGE, "b = %d outside 0..%d", b, h->P.B - 1);
+    *out_offset = (size_t)h->P.subs[b].psi;
+    return ok();
+}

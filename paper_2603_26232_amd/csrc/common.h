@@ -1,0 +1,83 @@
+// Internal declarations shared by the HIP translation units of libparaqaoa.
+// Nothing here is part of the public C ABI (include/paraqaoa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pq {
+
+// One tile = 2^12 amplitudes of one subgraph's state; a workgroup of 256
+// threads holds it in registers (16 amplitudes per thread) and exchanges
+// register layouts through LDS.
+constexpr int TILE_BITS = 12;
+constexpr int TILE = 1 << TILE_BITS;
+constexpr int THREADS = 256;
+constexpr int REGS = TILE / THREADS;  // 16
+constexpr int LDS_TILE = TILE + TILE / 16;  // one pad slot per 16 amplitudes
+constexpr int MAX_GROUPS = 4;  // qubit groups per subgraph (n <= 30)
+constexpr int MAX_P = 32;      // QAOA depth limit
+constexpr int MAX_K = 64;      // top-k limit
+constexpr int LUT_MAX = 2048;  // phase table entries per layer (sum of weights + 1)
+constexpr int SMALL_MAX_N = 12;  // n <= 12: the whole state is one workgroup's tile
+constexpr int B_GROUP_MAX = 8;   // active qubits of a strided (high) group
+
+// Per-subgraph descriptor, resident in the workspace.
+struct SubDesc {
+    int32_t n;        // qubits
+    int32_t ngroups;  // 1 for n <= 12, else 1 + ceil((n-12)/8)
+    int32_t gstart[MAX_GROUPS];  // first qubit of group g (group 0 starts at 0)
+    int32_t gsize[MAX_GROUPS];   // qubits in group g (group 0 has min(n, 12))
+    int32_t lut_len;  // sum of weights + 1 (phase table length per layer)
+    int32_t ntiles;   // max(1, 2^(n-12))
+    int32_t tile_base;  // first global tile index
+    int32_t nedges;
+    int32_t pad0, pad1;
+    uint64_t psi, lam, tab, tabB, lut, coef, edges;  // byte offsets into the workspace
+};
+
+// Which part of the circuit one tile pass applies (layers are 0-based,
+// -1 = absent). Forward: RX(pre), phase(ph), RX(post). Backward: unmix(pre)
+// with the beta-gradient, gamma-gradient + unphase(ph), unmix(post).
+struct PassOps {
+    int32_t group;
+    int32_t pre, ph, post;
+    int32_t init;      // forward: synthesise |+> instead of loading
+    int32_t epi_e;     // forward: write the <C> partial of each tile
+    int32_t fused;     // backward: forward RX(pre) + <C> + lambda = C psi first
+    int32_t last;      // backward: nothing needs storing
+};
+
+struct Partials {
+    double* e;   // [total_tiles]
+    double* gb;  // [(l*MAX_GROUPS + g) * total_tiles + tile]
+    double* gg;  // [l * total_tiles + tile]
+    int32_t total_tiles;
+};
+
+// ---- launchers (sim.hip) ----
+hipError_t launch_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
+                             hipStream_t s);
+hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, const double* gamma,
+                             const double* beta, hipStream_t s);
+hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
+                           PassOps ops, Partials part, int lut_max, hipStream_t s);
+hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
+                           PassOps ops, Partials part, int lut_max, hipStream_t s);
+hipError_t launch_small(uint8_t* ws, const SubDesc* subs, const int32_t* list, int nlist, int p,
+                        int grad, Partials part, int lut_max, hipStream_t s);
+hipError_t launch_reduce(const SubDesc* subs, int B, int p, int grad, Partials part, double* E,
+                         double* dgamma, double* dbeta, hipStream_t s);
+// ---- launchers (topk.hip) ----
+hipError_t launch_topk(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int B, int k,
+                       int canonical, uint64_t* keys_a, uint64_t* keys_b, uint32_t* idx,
+                       float* prob, hipStream_t s);
+// ---- launchers (cut.hip) ----
+hipError_t launch_maxcut_eval(int32_t nV, int64_t nE, const int32_t* u, const int32_t* v,
+                              const int32_t* w, int64_t A, const uint32_t* assign, int64_t* cut,
+                              hipStream_t s);
+hipError_t launch_adam(int32_t count, double* theta, const double* grad, double* m, double* v,
+                       int32_t* step, double lr, double b1, double b2, double eps, double sign,
+                       hipStream_t s);
+
+}  // namespace pq

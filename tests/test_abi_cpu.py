@@ -1,0 +1,134 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and rejects bad arguments before touching the device."""
+import numpy as np
+import pytest
+
+from paper_2603_26232_amd import _abi
+from paper_2603_26232_amd.partition import batch_arrays, bucket_edges, partition_chain, partition_equal
+from paper_2603_26232_amd import synth
+import oracle
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    names = _abi.header_functions()
+    assert "qaoa_batch_create" in names and "maxcut_eval" in names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/paraqaoa.h but not exported"
+
+
+def test_status_strings():
+    assert _abi.qaoa_status_string(0) == "ok"
+    assert _abi.qaoa_status_string(3) == "workspace too small"
+
+
+def _ws(sizes, edges, **kw):
+    nq, off, u, v, w = batch_arrays(sizes, edges)
+    return _abi.qaoa_workspace_bytes(len(sizes), nq, off, kw.get("w", w), kw.get("max_p", 3),
+                                     kw.get("max_k", 16), kw.get("flags", 0))
+
+
+def test_workspace_size_grows_with_state_and_gradient():
+    e = (np.array([0], np.int32), np.array([1], np.int32), np.array([1], np.int32))
+    a = _ws([14], [e])
+    b = _ws([15], [e])
+    c = _ws([15], [e], flags=_abi.QAOA_FLAG_GRADIENT)
+    assert 8 * (1 << 14) < a < b < c
+    assert c - b >= 8 * (1 << 15)  # the adjoint state
+
+
+@pytest.mark.parametrize("n,status", [(0, 2), (31, 2)])
+def test_qubit_range(n, status):
+    e = (np.zeros(0, np.int32),) * 3
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([n], [e])
+    assert ei.value.status == status
+
+
+def test_argument_errors():
+    e = (np.array([0], np.int32), np.array([1], np.int32), np.array([1], np.int32))
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([5], [e], max_p=0)
+    assert ei.value.status == 2
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([5], [e], max_k=65)
+    assert ei.value.status == 2
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([5], [e], flags=0x80)
+    assert ei.value.status == 1
+    heavy = (np.array([0], np.int32), np.array([1], np.int32), np.array([5000], np.int32))
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([5], [heavy])
+    assert ei.value.status == 6
+    neg = (np.array([0], np.int32), np.array([1], np.int32), np.array([-1], np.int32))
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([5], [neg])
+    assert ei.value.status == 1
+
+
+def test_create_validates_edges_before_any_device_work():
+    # bad local ids and self-loops are rejected on the host; no device pointer
+    # is needed to see it (a NULL workspace would be the next error)
+    for bad in [(0, 5), (2, 2), (-1, 1)]:
+        nq, off, u, v, w = batch_arrays([5], [(np.array([bad[0]], np.int32), np.array([bad[1]], np.int32),
+                                               np.array([1], np.int32))])
+        with pytest.raises(_abi.QaoaError) as ei:
+            _abi.qaoa_batch_create(1, nq, off, u, v, w, 2, 4, 0, 0, 1 << 20, 0)
+        assert ei.value.status == 1 and "invalid" in ei.value.detail
+    # well-formed edges, but no workspace
+    nq, off, u, v, w = batch_arrays([5], [(np.array([0], np.int32), np.array([1], np.int32),
+                                           np.array([1], np.int32))])
+    with pytest.raises(_abi.QaoaError) as ei:
+        _abi.qaoa_batch_create(1, nq, off, u, v, w, 2, 4, 0, 0, 1 << 20, 0)
+    assert ei.value.status == 1 and "workspace" in ei.value.detail
+    with pytest.raises(_abi.QaoaError) as ei:
+        _abi.qaoa_batch_create(1, nq, off, u, v, w, 2, 4, 0, 256, 16, 0)
+    assert ei.value.status == 3
+
+
+def test_calls_on_null_handle_are_rejected():
+    for fn, args in [(_abi.qaoa_apply_layers, (0, 1, 8, 8, 0)), (_abi.qaoa_expectation, (0, 8, 0)),
+                     (_abi.qaoa_topk, (0, 4, 8, 8, 0))]:
+        with pytest.raises(_abi.QaoaError) as ei:
+            fn(*args)
+        assert ei.value.status == 1
+    _abi.qaoa_batch_destroy(0)  # NULL is accepted
+
+
+# ---------------------------------------------------------------- host prep
+@pytest.mark.parametrize("nV,N", [(400, 20), (401, 20), (57, 5), (20, 20), (1000, 26)])
+def test_partition_matches_oracle(nV, N):
+    p = partition_equal(nV, N)
+    s, z = oracle.partition_equal(nV, N)
+    assert np.array_equal(p.start, s) and np.array_equal(p.size, z)
+
+
+def test_chain_partition_matches_oracle():
+    sizes = synth.ragged_sizes(1, 14, 26, 300)
+    p = partition_chain(2000, sizes)
+    s, z = oracle.partition_chain(2000, sizes)
+    assert np.array_equal(p.start, s) and np.array_equal(p.size, z)
+
+
+def test_bucketing_matches_getsubgraph():
+    g = synth.erdos_renyi(150, 0.08, 4)
+    p = partition_equal(150, 12)
+    subs, inter = bucket_edges(p, g.u, g.v, g.w)
+    total = sum(len(s[0]) for s in subs) + len(inter[0])
+    assert total == g.num_edges
+    for k in range(p.M):
+        ou, ov, ow = oracle.induced_edges(g.u, g.v, g.w, p.start[k], p.size[k])
+        assert np.array_equal(ou, subs[k][0]) and np.array_equal(ov, subs[k][1])
+
+
+def test_generators_shapes():
+    g = synth.erdos_renyi(400, 0.05, 0)
+    assert abs(g.num_edges - 0.05 * 400 * 399 / 2) < 4 * np.sqrt(3990)
+    assert np.all(g.u < g.v)
+    r = synth.random_regular3(26, 5)
+    deg = np.bincount(np.concatenate([r.u, r.v]), minlength=26)
+    assert np.all(deg == 3) and r.num_edges == 39
+    assert len(set(zip(r.u.tolist(), r.v.tolist()))) == 39
+    # counter-based stream: any window equals the same slice of a longer draw
+    a = synth.splitmix64(9, 0, 100)
+    assert np.array_equal(a[40:60], synth.splitmix64(9, 40, 20))
