@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the ParaQAOA hot path on one MI355X.
+
+One step = one whole plain-method solve of the 400-vertex workload: batch
+build with integer cut tables, 50 Adam steps of every subgraph's angles on
+exact adjoint gradients, the final state and <C>, top-16 extraction, the
+level-wise beam merge (W = 4096) and the integer CutVal of the winner.
+Workload: Erdos-Renyi G(400, 0.05), seed 0, unit weights, partitioned into
+21 chained subgraphs of 20 vertices (20 qubits, 2^20 complex64 amplitudes
+each), QAOA depth p = 3.
+
+value = amplitude updates per second: per forward evaluation every layer
+applies n RX gates and one diagonal phase to each amplitude, U = sum_b
+p (n_b + 1) 2^n_b; an optimiser step is a forward evaluation plus the
+adjoint sweep over two states (3 U), and the final evaluation adds U.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QAOA amp-updates/s + HBM GB/s; 2k-vertex solve time, learned vs plain angles"
+KERNELS = ["fwd_pass", "bwd_pass", "small", "cut_tables", "angle_prep", "reduce", "topk", "maxcut", "adam",
+           "merge"]
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_record(kernel):
+    """Measured HBM traffic per launch of `kernel` from the committed PMC
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_plain400.txt")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("RECORD "):
+            rec = json.loads(line[len("RECORD "):])
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2603_26232_amd", "csrc", rec.get("source", "sim.hip"))
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != rec.get("source_sha256"):
+        return None
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the hot path "
+              "shards by subgraph with no communication until the merge, which this box cannot show.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2603_26232_amd import synth, _abi
+    from paper_2603_26232_amd.partition import partition_equal
+    from paper_2603_26232_amd.solve import Solver, SolveConfig, cold_start
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    g = synth.erdos_renyi(400, 0.05, 0)
+    part = partition_equal(400, 20)
+    cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
+    log(f"bench: graph {g}, {part.M} subgraphs of sizes {sorted(set(part.size.tolist()))}, p={cfg.p}, "
+        f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
+    S = Solver(g, part, cfg)
+    U = sum(cfg.p * (int(n) + 1) * (1 << int(n)) for n in part.size)
+    updates_per_step = (3 * cfg.iters + 1) * U
+
+    def step():
+        S.rebuild()
+        S.run()
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps")
+    _abi.qaoa_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    for k in KERNELS:
+        n, ms, by = _abi.qaoa_profile_read(k)
+        if n:
+            kern[k] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n, "algo_bytes": by}
+    _abi.qaoa_profile_enable(0)
+    res = S.result()
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = updates_per_step * args.steps / elapsed
+    total_bytes = sum(v["algo_bytes"] for v in kern.values())
+    log(f"bench: {ms_step:.3f} ms/step, {value:.4e} amp-updates/s, cut {res.cut}")
+    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"]):
+        gbs = v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9 if v["total_ms"] > 0 else 0.0
+        log(f"  {k:11s} {v['launches']:6d} launches  avg {v['avg_us']:9.2f} us  {gbs:8.1f} GB/s algorithmic")
+
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    d = kern[dom]
+    achieved = d["algo_bytes"] / (d["total_ms"] * 1e-3) / 1e9
+    tr = traffic_record(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "algo_bytes_per_launch": d["algo_bytes"] / d["launches"], "avg_launch_us": round(d["avg_us"], 2),
+                "traffic": (None if tr is None else tr["hbm_bytes_per_launch"])}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "amp-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "plain-method solve, G(400,0.05) seed 0, 21 subgraphs x 20 qubits, p=3, "
+                               "50 Adam steps, top-16, beam 4096, CutVal",
+                   "vertices": 400, "edges": g.num_edges, "subgraphs": part.M, "qubits": 20, "p": cfg.p,
+                   "adam_steps": cfg.iters, "k": cfg.k, "beam": cfg.beam},
+        "hbm_gbs_step": total_bytes / args.steps / (elapsed / args.steps) / 1e9,
+        "roofline": roofline,
+        "solve": {"cut": res.cut, "sum_E": float(np.sum(res.energies))},
+        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
+                        "algo_GBs": round(v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] else 0}
+                    for k, v in kern.items()},
+    }
+    S.close()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        g0, b0 = cold_start(cfg.p, part.M)
+        T = args.cpu_iters
+        log(f"bench: CPU baseline: FP64 oracle, {part.M} subgraphs x ({T} Adam steps + final evaluation)")
+        c0 = time.perf_counter()
+        oracle.solve_batch(part.size, S.sub_edges, g0, b0, T, cfg.k, lr=cfg.lr)
+        c1 = time.perf_counter()
+        cpu_value = (3 * T + 1) * U / (c1 - c0)
+        out["cpu_baseline"] = {"value": cpu_value, "unit": "amp-updates/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": round(c1 - c0, 2),
+                               "sample": f"all {part.M} subgraphs of the 400-vertex workload, {T} Adam steps "
+                                         f"with adjoint gradients + final evaluation and top-{cfg.k} (FP64)"}
+        log(f"bench: CPU baseline {cpu_value:.4e} amp-updates/s in {c1 - c0:.1f} s on {oracle.num_threads()} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

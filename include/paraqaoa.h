@@ -163,6 +163,45 @@ qaoa_status_t maxcut_eval(int32_t num_vertices, int64_t num_edges, const int32_t
                           const int32_t* d_w, int64_t num_assign, const uint32_t* d_assign, int64_t* d_cut,
                           qaoa_stream_t stream);
 
+/* Workspace size for qaoa_merge_beam (device bytes, 256-byte aligned). */
+qaoa_status_t qaoa_merge_workspace_bytes(int32_t num_vertices, int32_t M, int64_t num_edges, int32_t K,
+                                         int32_t W, size_t* out_bytes);
+
+/* Level-Aware Merge (Sec. 3.4, Alg. 2) of the per-subgraph candidates into a
+ * full-graph assignment, as a level-wise beam of width W.
+ * Candidate set of subgraph i is B_i = {b_j, ~b_j} over the top-k bitstrings
+ * b_j; a path picks a member of B_1 and then, at each later level, the member
+ * of each pair whose bit for the vertex shared with the previous subgraph
+ * agrees with the path (2 K^M full paths). Paths are ordered as the
+ * depth-first traversal of Alg. 2 visits them (level 1 lists b_1, ~b_1, b_2,
+ * ~b_2, ...; later levels list by j). After each level the W paths with the
+ * largest cut over the edges whose endpoints are both assigned survive, ties
+ * broken by path order; the result is the best full path by (cut, path
+ * order). With W >= 2 K^(M-1) nothing is pruned and the result equals the
+ * exhaustive traversal of Alg. 2 (strict '>' keeps the first maximum).
+ *   num_vertices     |V|
+ *   M, h_start, h_size  host [M]: the chain partition; range i is
+ *                    [h_start[i], h_start[i] + h_size[i]), h_start[0] = 0,
+ *                    h_start[i] = h_start[i-1] + h_size[i-1] - 1, the last
+ *                    range ends at |V|; sizes 2..32 (1 allowed when M = 1)
+ *   num_edges, h_u, h_v, h_w  host full-graph edge list (ids in [0, |V|),
+ *                    u != v), weights >= 0 or NULL for unit weights
+ *   K, d_cand        device uint32 [M*K]: row i holds b_j of subgraph i in
+ *                    local bit order (bit t = vertex h_start[i] + t); the
+ *                    entries after the first 0xFFFFFFFF of a row are ignored
+ *   W                beam width, 1..8192
+ *   d_workspace      device, >= qaoa_merge_workspace_bytes, 256-byte aligned
+ *   d_best_assign    device uint32 [ceil(|V|/32)], the winning assignment
+ *                    (vertex t = word t/32, bit t%32; bit 1 = side S)
+ *   d_best_cut       device int64 [1], its cut value; -1 (and a zero
+ *                    assignment) if some row has no candidate
+ * The host arrays are copied (the call waits for that copy). */
+qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const int32_t* h_start, const int32_t* h_size,
+                              int64_t num_edges, const int32_t* h_u, const int32_t* h_v, const int32_t* h_w,
+                              int32_t K, const uint32_t* d_cand, int32_t W, void* d_workspace,
+                              size_t workspace_bytes, uint32_t* d_best_assign, int64_t* d_best_cut,
+                              qaoa_stream_t stream);
+
 /* Where subgraph b's state lives: the byte offset, inside the workspace, of
  * its 2^n complex64 amplitudes (interleaved real, imaginary; index z). After
  * qaoa_apply_layers they hold |psi>; after qaoa_expectation_grad they hold
@@ -176,14 +215,17 @@ const char* qaoa_status_string(qaoa_status_t s);
 const char* qaoa_last_error(void);
 
 /* Kernel timing for measurement: while enabled, the library brackets every
- * launch of its kernels with HIP events on the launch stream.
- * qaoa_profile_read waits for those events and returns, for the named
- * kernel ("fwd_pass", "bwd_pass", "small", "cut_tables", "angle_prep",
- * "reduce", "topk", "maxcut", "adam", "merge_expand", "merge_select"), the
- * number of launches and their summed duration in milliseconds since the
- * last qaoa_profile_enable(1). Not for use while another thread launches. */
+ * launch of its kernels with HIP events on the launch stream and adds up the
+ * launch's algorithmic HBM bytes (each state read and written once per pass,
+ * plus the uint16 cut table where the pass needs C(z)). qaoa_profile_read
+ * waits for those events and returns, for the named kernel ("fwd_pass",
+ * "bwd_pass", "small", "cut_tables", "angle_prep", "reduce", "topk",
+ * "maxcut", "adam", "merge", "mlp_forward", "mlp_backward"), the number of
+ * launches, their summed duration in milliseconds and their summed
+ * algorithmic bytes since the last qaoa_profile_enable(1). Not for use while
+ * another thread launches. */
 qaoa_status_t qaoa_profile_enable(int32_t on);
-qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms, double* algo_bytes);
 
 #ifdef __cplusplus
 }

@@ -510,18 +510,26 @@ static int cmp_paths(const void* pa, const void* pb)
 }
 
 /* cut of the edges completed at level i: max(u, v) is a vertex that first
- * appears in V_i (for i = 0 every vertex of V_0 is new). */
-static int64_t completed_cut(const merge_ctx* c, int32_t i, const uint8_t* x)
+ * appears in V_i (for i = 0 every vertex of V_0 is new). The edges of each
+ * level are listed once up front (lvl_edges[lvl_off[i] .. lvl_off[i+1])). */
+static int64_t completed_cut(const merge_ctx* c, const int64_t* lvl_off, const int64_t* lvl_edges, int32_t i,
+                             const uint8_t* x)
 {
-    int32_t lo = (i == 0) ? c->start[0] : c->start[i] + 1;
-    int32_t hi = c->start[i] + c->size[i];
     int64_t s = 0;
-    for (int64_t e = 0; e < c->nE; ++e) {
-        int32_t a = c->u[e], b = c->v[e];
-        int32_t mx = a > b ? a : b;
-        if (mx >= lo && mx < hi && x[a] != x[b]) s += weight_of(c->w, e);
+    for (int64_t q = lvl_off[i]; q < lvl_off[i + 1]; ++q) {
+        int64_t e = lvl_edges[q];
+        if (x[c->u[e]] != x[c->v[e]]) s += weight_of(c->w, e);
     }
     return s;
+}
+
+static int32_t first_level(const merge_ctx* c, int32_t vtx)
+{
+    for (int32_t i = 0; i < c->M; ++i) {
+        int32_t lo = (i == 0) ? c->start[0] : c->start[i] + 1;
+        if (vtx >= lo && vtx < c->start[i] + c->size[i]) return i;
+    }
+    return -1;
 }
 
 int64_t or_merge(int32_t nV, int32_t M, const int32_t* start, const int32_t* size, int64_t nE,
@@ -555,8 +563,25 @@ int64_t or_merge(int32_t nV, int32_t M, const int32_t* start, const int32_t* siz
         free(c.Ki);
         return best;
     }
-    /* beam */
-    int64_t cap = W * (int64_t)(K > 2 ? K : 2);
+    /* beam: bucket the edges by the level that completes them */
+    int64_t* lvl_off = (int64_t*)calloc((size_t)M + 1, sizeof(int64_t));
+    int64_t* lvl_edges = (int64_t*)malloc((size_t)(nE > 0 ? nE : 1) * sizeof(int64_t));
+    int32_t* lvl_of = (int32_t*)malloc((size_t)(nE > 0 ? nE : 1) * sizeof(int32_t));
+    for (int64_t e = 0; e < nE; ++e) {
+        int32_t mx = u[e] > v[e] ? u[e] : v[e];
+        lvl_of[e] = first_level(&c, mx);
+        lvl_off[lvl_of[e] + 1] += 1;
+    }
+    for (int32_t i = 0; i < M; ++i) lvl_off[i + 1] += lvl_off[i];
+    {
+        int64_t* fill = (int64_t*)malloc(((size_t)M + 1) * sizeof(int64_t));
+        memcpy(fill, lvl_off, ((size_t)M + 1) * sizeof(int64_t));
+        for (int64_t e = 0; e < nE; ++e) lvl_edges[fill[lvl_of[e]]++] = e;
+        free(fill);
+    }
+    /* level 1 creates 2 K paths, later levels at most W K */
+    int64_t cap = W * (int64_t)K;
+    if (cap < 2 * (int64_t)K) cap = 2 * (int64_t)K;
     beam_path* cur = (beam_path*)calloc((size_t)cap, sizeof(beam_path));
     beam_path* nxt = (beam_path*)calloc((size_t)cap, sizeof(beam_path));
     for (int64_t r = 0; r < cap; ++r) {
@@ -571,7 +596,7 @@ int64_t or_merge(int32_t nV, int32_t M, const int32_t* start, const int32_t* siz
             beam_path* q = &nxt[ncur++];
             assign_level(&c, 0, cand[j], o, q->x);
             q->digits[0] = 2 * j + o;
-            q->score = completed_cut(&c, 0, q->x);
+            q->score = completed_cut(&c, lvl_off, lvl_edges, 0, q->x);
         }
     for (int32_t i = 0;; ++i) {
         g_sort_len = i + 1;
@@ -592,7 +617,7 @@ int64_t or_merge(int32_t nV, int32_t M, const int32_t* start, const int32_t* siz
                 int32_t o = (int32_t)((b & 1u) ^ q->x[start[lvl]]);
                 assign_level(&c, lvl, b, o, q->x);
                 q->digits[lvl] = j;
-                q->score = cur[r].score + completed_cut(&c, lvl, q->x);
+                q->score = cur[r].score + completed_cut(&c, lvl_off, lvl_edges, lvl, q->x);
             }
         ncur = nn;
         if (lvl == M - 1) *leaves = (double)nn;
@@ -610,5 +635,8 @@ int64_t or_merge(int32_t nV, int32_t M, const int32_t* start, const int32_t* siz
     free(cur);
     free(nxt);
     free(c.Ki);
+    free(lvl_off);
+    free(lvl_edges);
+    free(lvl_of);
     return best;
 }

@@ -64,14 +64,14 @@ def lib() -> ct.CDLL:
             "qaoa_expectation_grad": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
             "qaoa_adam_step": [_i32, _vp, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _vp],
             "maxcut_eval": [_i32, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp],
-            "qaoa_merge_workspace_bytes": [_i32, _i32, _vp, _i64, _vp, _vp, _i32, _i32, _vp],
+            "qaoa_merge_workspace_bytes": [_i32, _i32, _i64, _i32, _i32, _vp],
             "qaoa_merge_beam": [_i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp,
                                 ct.c_size_t, _vp, _vp, _vp],
             "qaoa_mlp_forward": [_i32, _vp, _vp, _vp, _vp, _vp],
             "qaoa_mlp_backward": [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
             "qaoa_state_offset": [_vp, _i32, _vp],
             "qaoa_profile_enable": [_i32],
-            "qaoa_profile_read": [ct.c_char_p, _vp, _vp],
+            "qaoa_profile_read": [ct.c_char_p, _vp, _vp, _vp],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -174,11 +174,9 @@ def maxcut_eval(num_vertices: int, num_edges: int, d_u: int, d_v: int, d_w, num_
           _vp(d_assign), _vp(d_cut), _vp(stream))
 
 
-def qaoa_merge_workspace_bytes(num_vertices, M, h_size, num_edges, h_u, h_v, K, W) -> int:
-    sz, u, v = _ai32(h_size), _ai32(h_u), _ai32(h_v)
+def qaoa_merge_workspace_bytes(num_vertices, M, num_edges, K, W) -> int:
     out = ct.c_size_t(0)
-    _call("qaoa_merge_workspace_bytes", num_vertices, M, _np_ptr(sz), num_edges, _np_ptr(u), _np_ptr(v),
-          K, W, ct.byref(out))
+    _call("qaoa_merge_workspace_bytes", num_vertices, M, num_edges, K, W, ct.byref(out))
     return int(out.value)
 
 
@@ -213,7 +211,9 @@ def qaoa_profile_enable(on: int) -> None:
 
 
 def qaoa_profile_read(kernel: str):
+    """(launches, total_ms, algorithmic_bytes) of a kernel since profiling began."""
     n = ct.c_int64(0)
     ms = ct.c_double(0.0)
-    _call("qaoa_profile_read", kernel.encode(), ct.byref(n), ct.byref(ms))
-    return int(n.value), float(ms.value)
+    by = ct.c_double(0.0)
+    _call("qaoa_profile_read", kernel.encode(), ct.byref(n), ct.byref(ms), ct.byref(by))
+    return int(n.value), float(ms.value), float(by.value)

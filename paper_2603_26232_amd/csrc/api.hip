@@ -51,6 +51,7 @@ struct ProfRec {
 struct Profiler {
     bool on = false;
     std::map<std::string, std::vector<ProfRec>> recs;
+    std::map<std::string, double> bytes;  // algorithmic bytes of the recorded launches
     std::vector<ProfRec> pool;
 };
 Profiler g_prof;
@@ -60,9 +61,10 @@ struct ProfScope {
     hipStream_t s;
     ProfRec r{};
     bool active;
-    ProfScope(const char* n, hipStream_t st) : name(n), s(st), active(g_prof.on)
+    ProfScope(const char* n, hipStream_t st, double algo_bytes = 0.0) : name(n), s(st), active(g_prof.on)
     {
         if (!active) return;
+        g_prof.bytes[name] += algo_bytes;
         if (!g_prof.pool.empty()) {
             r = g_prof.pool.back();
             g_prof.pool.pop_back();
@@ -89,15 +91,18 @@ extern "C" qaoa_status_t qaoa_profile_enable(int32_t on)
             g_prof.pool.push_back(r);
         }
     g_prof.recs.clear();
+    g_prof.bytes.clear();
     g_prof.on = on != 0;
     return ok();
 }
 
-extern "C" qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms)
+extern "C" qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms,
+                                           double* algo_bytes)
 {
-    if (!kernel || !launches || !total_ms) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
+    if (!kernel || !launches || !total_ms || !algo_bytes) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
     *launches = 0;
     *total_ms = 0.0;
+    *algo_bytes = g_prof.bytes.count(kernel) ? g_prof.bytes[kernel] : 0.0;
     auto it = g_prof.recs.find(kernel);
     if (it == g_prof.recs.end()) return ok();
     for (auto& r : it->second) {
@@ -305,6 +310,40 @@ std::vector<PassOps> group_passes(const std::vector<Op>& ops)
     return out;
 }
 
+// Algorithmic HBM bytes of one tile pass: every state it touches read once
+// and written once (complex64, 8 B per amplitude) plus the uint16 cut table
+// when the pass needs C(z).
+double pass_bytes(const PassOps& o, bool backward, int nwork)
+{
+    const double amps = (double)nwork * TILE;
+    double per;
+    if (!backward) {
+        per = (o.init ? 8.0 : 16.0) + ((o.ph >= 0 || o.epi_e) ? 2.0 : 0.0);
+    } else if (o.fused) {
+        per = 8.0 + 8.0 + 2.0;  // read psi, write lambda, cut table
+    } else {
+        per = 16.0 + (o.last ? 0.0 : 16.0) + (o.ph >= 0 ? 2.0 : 0.0);
+    }
+    return per * amps;
+}
+
+double angle_bytes(const Plan& P, int p)
+{
+    double b = 0.0;
+    for (const SubDesc& d : P.subs) b += (double)p * (d.lut_len * 8.0 + 8.0 + 16.0);
+    return b;
+}
+
+// whole-state-in-LDS kernel: cut table once per layer (and per adjoint layer),
+// the state written once (forward)
+double small_bytes(const Plan& P, int p, bool grad)
+{
+    double b = 0.0;
+    for (const SubDesc& d : P.subs)
+        if (d.ngroups == 1) b += (double)(1ull << d.n) * (grad ? 2.0 * (2 * p + 2) : (2.0 * (p + 1) + 8.0));
+    return b;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -406,7 +445,9 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
     h->part.gg = (double*)(ws + h->P.o_pgg);
     h->part.total_tiles = h->P.total_tiles;
     {
-        ProfScope ps("cut_tables", st);
+        double tb = 0.0;
+        for (const SubDesc& d : h->P.subs) tb += (double)(1ull << d.n) * (d.ngroups >= 2 ? 4.0 : 2.0);
+        ProfScope ps("cut_tables", st, tb);
         hipError_t e = launch_cut_tables(ws, h->d_subs, (const int2*)(ws + h->P.o_work_all), h->P.total_tiles, st);
         if (e != hipSuccess) {
             delete h;
@@ -439,11 +480,11 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
     hipStream_t st = (hipStream_t)stream;
     Plan& P = h->P;
     {
-        ProfScope ps("angle_prep", st);
+        ProfScope ps("angle_prep", st, angle_bytes(P, p));
         HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
     }
     if (P.nsmall) {
-        ProfScope ps("small", st);
+        ProfScope ps("small", st, small_bytes(P, p, false));
         HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 0, h->part,
                              P.lut_max, st));
     }
@@ -454,7 +495,7 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
             PassOps o = passes[i];
             o.init = i == 0;
             o.epi_e = i + 1 == passes.size();
-            ProfScope ps("fwd_pass", st);
+            ProfScope ps("fwd_pass", st, pass_bytes(o, false, P.nwork_cls[G]));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_cls[G]), P.nwork_cls[G], o,
                                     h->part, P.lut_max, st));
         }
@@ -470,7 +511,7 @@ extern "C" qaoa_status_t qaoa_expectation(qaoa_batch_t h, double* d_out, qaoa_st
     if (!d_out) return fail(QAOA_ERR_INVALID_ARG, "d_out is NULL");
     if (!h->e_valid) return fail(QAOA_ERR_STATE, "no state: call qaoa_apply_layers first");
     hipStream_t st = (hipStream_t)stream;
-    ProfScope ps("reduce", st);
+    ProfScope ps("reduce", st, 8.0 * h->P.total_tiles);
     HIP_TRY(launch_reduce(h->d_subs, h->P.B, 1, 0, h->part, d_out, nullptr, nullptr, st));
     return ok();
 }
@@ -483,7 +524,9 @@ extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, f
     if (!h->state_valid) return fail(QAOA_ERR_STATE, "no ansatz state: call qaoa_apply_layers first");
     hipStream_t st = (hipStream_t)stream;
     const Plan& P = h->P;
-    ProfScope ps("topk", st);
+    double tk = 0.0;
+    for (const SubDesc& d : P.subs) tk += (double)(1ull << d.n) * 8.0;
+    ProfScope ps("topk", st, tk + 16.0 * P.total_tiles * k);
     HIP_TRY(launch_topk(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_all), P.total_tiles, P.B, k,
                         (P.flags & QAOA_FLAG_TOPK_RAW) ? 0 : 1, (uint64_t*)(h->ws + P.o_keys), nullptr, d_idx,
                         d_prob, st));
@@ -502,11 +545,11 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
     hipStream_t st = (hipStream_t)stream;
     Plan& P = h->P;
     {
-        ProfScope ps("angle_prep", st);
+        ProfScope ps("angle_prep", st, angle_bytes(P, p));
         HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
     }
     if (P.nsmall) {
-        ProfScope ps("small", st);
+        ProfScope ps("small", st, small_bytes(P, p, true));
         HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 1, h->part,
                              P.lut_max, st));
     }
@@ -519,7 +562,7 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         for (size_t i = 0; i + 1 < fwd.size(); ++i) {
             PassOps o = fwd[i];
             o.init = i == 0;
-            ProfScope ps("fwd_pass", st);
+            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, o, h->part, P.lut_max, st));
         }
         std::vector<Op> rev(ops.rbegin(), ops.rend());
@@ -529,18 +572,18 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         PassOps f = fwd.back();
         f.fused = 1;
         {
-            ProfScope ps("bwd_pass", st);
+            ProfScope ps("bwd_pass", st, pass_bytes(f, true, nw));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, f, h->part, P.lut_max, st));
         }
         for (size_t i = 1; i < bwd.size(); ++i) {
             PassOps o = bwd[i];
             o.last = i + 1 == bwd.size();
-            ProfScope ps("bwd_pass", st);
+            ProfScope ps("bwd_pass", st, pass_bytes(o, true, nw));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, o, h->part, P.lut_max, st));
         }
     }
     {
-        ProfScope ps("reduce", st);
+        ProfScope ps("reduce", st, 8.0 * P.total_tiles * (1.0 + p * (MAX_GROUPS + 1.0)));
         HIP_TRY(launch_reduce(h->d_subs, P.B, p, 1, h->part, d_E, d_dgamma, d_dbeta, st));
     }
     h->state_valid = false;
@@ -557,7 +600,7 @@ extern "C" qaoa_status_t qaoa_adam_step(int32_t count, double* d_theta, const do
     if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && lr >= 0.0))
         return fail(QAOA_ERR_OUT_OF_RANGE, "Adam constants out of range");
     hipStream_t st = (hipStream_t)stream;
-    ProfScope ps("adam", st);
+    ProfScope ps("adam", st, 7.0 * 8.0 * count);
     HIP_TRY(launch_adam(count, d_theta, d_grad, d_m, d_v, d_step, lr, beta1, beta2, eps, maximise ? 1.0 : -1.0, st));
     return ok();
 }
@@ -571,7 +614,8 @@ extern "C" qaoa_status_t maxcut_eval(int32_t num_vertices, int64_t num_edges, co
     if (num_edges > 0 && (!d_u || !d_v)) return fail(QAOA_ERR_INVALID_ARG, "d_u/d_v are NULL");
     if (num_assign > 0 && (!d_assign || !d_cut)) return fail(QAOA_ERR_INVALID_ARG, "d_assign/d_cut are NULL");
     hipStream_t st = (hipStream_t)stream;
-    ProfScope ps("maxcut", st);
+    ProfScope ps("maxcut", st, (double)num_edges * (d_w ? 12.0 : 8.0) * (num_assign > 0 ? 1.0 : 0.0) +
+                                   4.0 * num_assign * ((num_vertices + 31) / 32) + 8.0 * num_assign);
     HIP_TRY(launch_maxcut_eval(num_vertices, num_edges, d_u, d_v, d_w, num_assign, d_assign, d_cut, st));
     return ok();
 }
@@ -581,5 +625,172 @@ extern "C" qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* ou
     if (!h || !out_offset) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
     if (b < 0 || b >= h->P.B) return fail(QAOA_ERR_OUT_OF_RANGE, "b = %d outside 0..%d", b, h->P.B - 1);
     *out_offset = (size_t)h->P.subs[b].psi;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// merge (Sec. 3.4, Alg. 2): host preparation of the level structure
+// ---------------------------------------------------------------------------
+namespace {
+struct MergePlan {
+    uint64_t o_lv, o_intra, o_back, o_ccut, o_keys, o_surv, o_counts, o_rows0, o_rows1, o_scores, total;
+    int nw;
+};
+
+MergePlan merge_plan(int32_t nV, int32_t M, int64_t nE, int32_t K, int32_t W)
+{
+    MergePlan P{};
+    P.nw = (nV + 31) / 32;
+    uint64_t o = 0;
+    auto region = [&](uint64_t bytes) {
+        o = align_up(o, 256);
+        const uint64_t r = o;
+        o += bytes;
+        return r;
+    };
+    const uint64_t nkeys = std::max<uint64_t>((uint64_t)W * K, 2ull * K);
+    P.o_lv = region(sizeof(MergeLevel) * M);
+    P.o_intra = region(sizeof(int32_t) * 3 * (nE + 1));
+    P.o_back = region(sizeof(int32_t) * 3 * (nE + 1));
+    P.o_ccut = region(sizeof(int64_t) * M * K);
+    P.o_keys = region(sizeof(uint64_t) * nkeys);
+    P.o_surv = region(sizeof(Surv) * W);
+    P.o_counts = region(sizeof(int32_t) * 4);
+    P.o_rows0 = region(sizeof(uint32_t) * (uint64_t)W * P.nw);
+    P.o_rows1 = region(sizeof(uint32_t) * (uint64_t)W * P.nw);
+    P.o_scores = region(sizeof(int64_t) * W);
+    P.total = align_up(o, 4096);
+    return P;
+}
+
+qaoa_status_t merge_check(int32_t nV, int32_t M, int64_t nE, int32_t K, int32_t W)
+{
+    if (nV < 1 || M < 1) return fail(QAOA_ERR_INVALID_ARG, "num_vertices = %d, M = %d", nV, M);
+    if (nE < 0) return fail(QAOA_ERR_INVALID_ARG, "num_edges < 0");
+    if (K < 1 || K > MAX_K) return fail(QAOA_ERR_OUT_OF_RANGE, "K = %d outside 1..%d", K, MAX_K);
+    if (W < 1 || W > QAOA_MAX_BEAM) return fail(QAOA_ERR_OUT_OF_RANGE, "W = %d outside 1..%d", W, QAOA_MAX_BEAM);
+    return QAOA_OK;
+}
+}  // namespace
+
+extern "C" qaoa_status_t qaoa_merge_workspace_bytes(int32_t num_vertices, int32_t M, int64_t num_edges, int32_t K,
+                                                    int32_t W, size_t* out_bytes)
+{
+    if (!out_bytes) return fail(QAOA_ERR_INVALID_ARG, "out_bytes is NULL");
+    qaoa_status_t s = merge_check(num_vertices, M, num_edges, K, W);
+    if (s != QAOA_OK) return s;
+    *out_bytes = (size_t)merge_plan(num_vertices, M, num_edges, K, W).total;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const int32_t* h_start,
+                                         const int32_t* h_size, int64_t num_edges, const int32_t* h_u,
+                                         const int32_t* h_v, const int32_t* h_w, int32_t K, const uint32_t* d_cand,
+                                         int32_t W, void* d_workspace, size_t workspace_bytes,
+                                         uint32_t* d_best_assign, int64_t* d_best_cut, qaoa_stream_t stream)
+{
+    qaoa_status_t s = merge_check(num_vertices, M, num_edges, K, W);
+    if (s != QAOA_OK) return s;
+    if (!h_start || !h_size) return fail(QAOA_ERR_INVALID_ARG, "h_start/h_size are NULL");
+    if (num_edges > 0 && (!h_u || !h_v)) return fail(QAOA_ERR_INVALID_ARG, "h_u/h_v are NULL");
+    if (!d_cand || !d_best_assign || !d_best_cut) return fail(QAOA_ERR_INVALID_ARG, "device pointer is NULL");
+    if (!d_workspace || ((uintptr_t)d_workspace) % 256)
+        return fail(QAOA_ERR_INVALID_ARG, "d_workspace NULL or not 256-byte aligned");
+    const MergePlan P = merge_plan(num_vertices, M, num_edges, K, W);
+    if (workspace_bytes < P.total)
+        return fail(QAOA_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %llu", workspace_bytes,
+                    (unsigned long long)P.total);
+    // chain: contiguous ranges sharing one vertex, covering [0, nV)
+    if (h_start[0] != 0 || h_start[M - 1] + h_size[M - 1] != num_vertices)
+        return fail(QAOA_ERR_INVALID_ARG, "ranges do not cover [0, %d)", num_vertices);
+    for (int i = 0; i < M; ++i) {
+        if (h_size[i] < (M > 1 ? 2 : 1) || h_size[i] > MERGE_MAX_SIZE)
+            return fail(QAOA_ERR_OUT_OF_RANGE, "subgraph %d has %d vertices (2..%d)", i, h_size[i], MERGE_MAX_SIZE);
+        if (i > 0 && h_start[i] != h_start[i - 1] + h_size[i - 1] - 1)
+            return fail(QAOA_ERR_INVALID_ARG, "subgraph %d does not start at the last vertex of %d", i, i - 1);
+    }
+    // level at which each vertex is first assigned
+    std::vector<int32_t> first(num_vertices);
+    for (int i = 0; i < M; ++i)
+        for (int v = h_start[i] + (i > 0 ? 1 : 0); v < h_start[i] + h_size[i]; ++v) first[v] = i;
+    std::vector<MergeLevel> lv(M);
+    std::vector<std::vector<int32_t>> intra(M), backk(M);
+    int64_t wsum = 0;
+    for (int64_t e = 0; e < num_edges; ++e) {
+        const int32_t a = h_u[e], b = h_v[e], w = h_w ? h_w[e] : 1;
+        if (a < 0 || b < 0 || a >= num_vertices || b >= num_vertices || a == b)
+            return fail(QAOA_ERR_INVALID_ARG, "edge %lld = (%d, %d) invalid", (long long)e, a, b);
+        if (w < 0) return fail(QAOA_ERR_INVALID_ARG, "edge %lld has negative weight", (long long)e);
+        wsum += w;
+        const int32_t lo = std::min(a, b), hi = std::max(a, b);
+        const int L = first[hi];
+        const int32_t st = h_start[L];
+        if (lo >= st) {
+            intra[L].push_back(lo - st);
+            intra[L].push_back(hi - st);
+            intra[L].push_back(w);
+        } else {
+            backk[L].push_back(lo);
+            backk[L].push_back(hi - st);
+            backk[L].push_back(w);
+        }
+    }
+    if (wsum > 0x7FFFFFF0ll) return fail(QAOA_ERR_NOT_SUPPORTED, "total weight %lld too large", (long long)wsum);
+    const uint64_t meta_end = P.o_ccut;
+    std::vector<uint8_t> img(meta_end, 0);
+    int32_t* I = (int32_t*)(img.data() + P.o_intra);
+    int32_t* Bk = (int32_t*)(img.data() + P.o_back);
+    int32_t io = 0, bo = 0;
+    for (int i = 0; i < M; ++i) {
+        MergeLevel& L = lv[i];
+        memset(&L, 0, sizeof(L));
+        L.start = h_start[i];
+        L.size = h_size[i];
+        L.intra_off = io;
+        L.intra_cnt = (int32_t)(intra[i].size() / 3);
+        memcpy(I + 3 * (size_t)io, intra[i].data(), intra[i].size() * sizeof(int32_t));
+        io += L.intra_cnt;
+        // back edges sorted by local endpoint k (counting sort, stable)
+        const int nb = (int)(backk[i].size() / 3);
+        int cnt[33] = {0};
+        for (int e = 0; e < nb; ++e) cnt[backk[i][3 * e + 1] + 1]++;
+        for (int k = 0; k < 32; ++k) cnt[k + 1] += cnt[k];
+        for (int k = 0; k <= 32; ++k) L.kbeg[k] = cnt[k];
+        L.back_off = bo;
+        int fill[33];
+        memcpy(fill, cnt, sizeof(fill));
+        for (int e = 0; e < nb; ++e) {
+            const int k = backk[i][3 * e + 1];
+            const int slot = bo + fill[k]++;
+            Bk[3 * (size_t)slot] = backk[i][3 * e];
+            Bk[3 * (size_t)slot + 1] = k;
+            Bk[3 * (size_t)slot + 2] = backk[i][3 * e + 2];
+            L.wk[k] += backk[i][3 * e + 2];
+        }
+        bo += nb;
+    }
+    memcpy(img.data() + P.o_lv, lv.data(), sizeof(MergeLevel) * M);
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* ws = (uint8_t*)d_workspace;
+    void* pinned = nullptr;
+    HIP_TRY(hipHostMalloc(&pinned, meta_end, hipHostMallocDefault));
+    memcpy(pinned, img.data(), meta_end);
+    hipError_t e1 = hipMemcpyAsync(ws, pinned, meta_end, hipMemcpyHostToDevice, st);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(st) : e1;
+    (void)hipHostFree(pinned);
+    if (e2 != hipSuccess) return fail(QAOA_ERR_HIP, "merge metadata upload: %s", hipGetErrorString(e2));
+    MergeBufs m;
+    m.lv = (const MergeLevel*)(ws + P.o_lv);
+    m.intra = (const int32_t*)(ws + P.o_intra);
+    m.back = (const int32_t*)(ws + P.o_back);
+    m.ccut = (int64_t*)(ws + P.o_ccut);
+    m.keys = (uint64_t*)(ws + P.o_keys);
+    m.surv = (Surv*)(ws + P.o_surv);
+    m.counts = (int32_t*)(ws + P.o_counts);
+    m.rows[0] = (uint32_t*)(ws + P.o_rows0);
+    m.rows[1] = (uint32_t*)(ws + P.o_rows1);
+    m.scores = (int64_t*)(ws + P.o_scores);
+    ProfScope ps("merge", st, 0.0);
+    HIP_TRY(launch_merge(m, M, K, W, P.nw, num_vertices, d_cand, d_best_assign, d_best_cut, st));
     return ok();
 }

@@ -55,6 +55,39 @@ struct Partials {
     int32_t total_tiles;
 };
 
+// ---- merge (merge.hip) ----
+struct MergeLevel {
+    int32_t start, size;
+    int32_t intra_off, intra_cnt;  // intra edges (local a, local b, w)
+    int32_t back_off;              // back edges (global u, local k, w), sorted by k
+    int32_t pad;
+    int32_t kbeg[33];              // back edges into local k: [back_off + kbeg[k], back_off + kbeg[k+1])
+    int32_t pad2[3];
+    int64_t wk[32];                // total back weight into local k
+};
+
+struct Surv {
+    int32_t parent;  // rank of the parent path (level 1: 0)
+    int32_t digit;   // j (level 1: 2j + o)
+    int64_t score;
+};
+
+struct MergeBufs {
+    const MergeLevel* lv;
+    const int32_t* intra;
+    const int32_t* back;
+    int64_t* ccut;
+    uint64_t* keys;
+    Surv* surv;
+    int32_t* counts;  // [0] = current paths, [1] = survivors
+    uint32_t* rows[2];
+    int64_t* scores;
+};
+
+hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV, const uint32_t* cand,
+                        uint32_t* best, int64_t* best_cut, hipStream_t s);
+constexpr int MERGE_MAX_SIZE = 32;  // vertices per level (one uint32 bitstring)
+
 // ---- launchers (sim.hip) ----
 hipError_t launch_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
                              hipStream_t s);

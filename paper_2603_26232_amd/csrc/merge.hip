@@ -1,0 +1,293 @@
+// Merge of the per-subgraph candidate sets (paper Sec. 3.4, Alg. 2) as a
+// level-wise beam on the GPU.
+//
+// Level i holds the chain subgraph V_i = [start_i, start_i + size_i); V_i
+// shares its first vertex with V_{i-1}. Candidate set B_i = {b_j, ~b_j}; a
+// path takes one member of B_1, then at every later level the member of each
+// pair whose bit for the shared vertex agrees with the path (so a path has
+// 2K choices at level 1 and K at each later level: 2 K^M leaves). Path order
+// is the depth-first order of Alg. 2 (digits 2j+o at level 1, j later).
+//
+// Score of a partial path = cut of the edges whose endpoints are both
+// assigned. By the cut decomposition of Sec. 3.4.1 a child's score is its
+// parent's plus C_i(b_j) (the intra-subgraph cut, orientation free) plus the
+// back edges (u assigned earlier, v new in V_i): sum_k (y_k ? W_k - A_k : A_k)
+// with y_k the child's bit for local vertex k, W_k the back-edge weight into
+// k and A_k the weight of those back edges whose earlier endpoint is 1 in the
+// parent. After each level the W best paths by (score desc, path order asc)
+// survive; with W >= 2 K^(M-1) this is the exhaustive merge.
+//
+// Keys: (score + 1) << 32 | (0xFFFFFFFF - order), order = parent_rank * K + j
+// (level 1: 2j + o); zero marks an invalid candidate. Survivors are kept in
+// path order, so a survivor's rank is its position.
+#include "common.h"
+
+namespace pq {
+
+__device__ inline int level_k(const uint32_t* cand, int K, int i)
+{
+    int k = 0;
+    while (k < K && cand[(size_t)i * K + k] != 0xFFFFFFFFu) ++k;
+    return k;
+}
+
+// C_i(b_j) for every level and candidate
+__global__ void k_merge_intra(const MergeLevel* lv, const int32_t* intra, const uint32_t* cand, int K,
+                              int64_t* ccut)
+{
+    const int i = blockIdx.x;
+    const MergeLevel L = lv[i];
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        const uint32_t b = cand[(size_t)i * K + j];
+        int64_t c = 0;
+        if (b != 0xFFFFFFFFu) {
+            for (int e = 0; e < L.intra_cnt; ++e) {
+                const int32_t* E = intra + 3 * (size_t)(L.intra_off + e);
+                if (((b >> E[0]) ^ (b >> E[1])) & 1u) c += E[2];
+            }
+        }
+        ccut[(size_t)i * K + j] = c;
+    }
+}
+
+// level 1: the 2 K_1 paths (j, o) in order b_1, ~b_1, b_2, ~b_2, ...
+__global__ void k_merge_first(const uint32_t* cand, int K, const int64_t* ccut, uint64_t* keys)
+{
+    const int Kv = level_k(cand, K, 0);
+    for (int d = threadIdx.x; d < 2 * K; d += blockDim.x) {
+        const int j = d >> 1;
+        uint64_t key = 0;
+        if (j < Kv) key = ((uint64_t)(ccut[j] + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)d);
+        keys[d] = key;
+    }
+}
+
+__device__ inline uint32_t row_bit(const uint32_t* row, int v) { return (row[v >> 5] >> (v & 31)) & 1u; }
+
+// level i >= 1: one block per parent path, one thread per candidate j
+__global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back, const uint32_t* cand, int K,
+                               const int64_t* ccut, const uint32_t* rows, int nw, const int64_t* scores,
+                               const int32_t* npaths, uint64_t* keys)
+{
+    __shared__ int64_t A[32];
+    const int p = blockIdx.x;
+    if (p >= *npaths) return;
+    const MergeLevel L = lv[i];
+    const uint32_t* row = rows + (size_t)p * nw;
+    for (int k = threadIdx.x; k < 32; k += blockDim.x) {
+        int64_t a = 0;
+        if (k < L.size) {
+            for (int e = L.kbeg[k]; e < L.kbeg[k + 1]; ++e) {
+                const int32_t* E = back + 3 * (size_t)(L.back_off + e);
+                if (row_bit(row, E[0])) a += E[2];
+            }
+        }
+        A[k] = a;
+    }
+    __syncthreads();
+    const int Kv = level_k(cand, K, i);
+    const uint32_t xs = row_bit(row, L.start);
+    const int64_t ps = scores[p];
+    for (int j = threadIdx.x; j < K; j += blockDim.x) {
+        uint64_t key = 0;
+        if (j < Kv) {
+            const uint32_t b = cand[(size_t)i * K + j];
+            const uint32_t o = (b & 1u) ^ xs;
+            int64_t s = ps + ccut[(size_t)i * K + j];
+            for (int k = 1; k < L.size; ++k) {
+                const uint32_t y = ((b >> k) & 1u) ^ o;
+                s += y ? (L.wk[k] - A[k]) : A[k];
+            }
+            const uint32_t order = (uint32_t)p * (uint32_t)K + (uint32_t)j;
+            key = ((uint64_t)(s + 1) << 32) | (uint64_t)(0xFFFFFFFFu - order);
+        }
+        keys[(size_t)p * K + j] = key;
+    }
+}
+
+constexpr int SEL_THREADS = 1024;
+constexpr int SEL_MAX = 8192;  // largest beam width
+
+// Keep the Wsel largest keys among keys[0..N); write them in path order as
+// survivors and their count. One workgroup: radix select on 8-bit digits,
+// compaction, then a bitonic sort on the order word.
+__global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* keys, const int32_t* Nptr, int Kmul,
+                                                              int Wsel, int first, Surv* surv, int32_t* nsurv)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sel[SEL_MAX];
+    __shared__ uint64_t s_prefix, s_mask;
+    __shared__ int32_t s_remaining, s_count, s_nnz;
+    const int tid = threadIdx.x;
+    const int64_t N = (int64_t)(*Nptr) * Kmul;
+    if (tid == 0) {
+        s_nnz = 0;
+        s_count = 0;
+    }
+    __syncthreads();
+    int nnz_local = 0;
+    for (int64_t q = tid; q < N; q += SEL_THREADS) nnz_local += keys[q] != 0ull;
+    atomicAdd(&s_nnz, nnz_local);
+    __syncthreads();
+    const int nnz = s_nnz;
+    uint64_t thr = 1ull;  // select every nonzero key when there are at most Wsel
+    if (nnz > Wsel) {
+        if (tid == 0) {
+            s_prefix = 0;
+            s_mask = 0;
+            s_remaining = Wsel;
+        }
+        __syncthreads();
+        for (int pos = 7; pos >= 0; --pos) {
+            for (int b = tid; b < 256; b += SEL_THREADS) hist[b] = 0;
+            __syncthreads();
+            const uint64_t prefix = s_prefix, mask = s_mask;
+            for (int64_t q = tid; q < N; q += SEL_THREADS) {
+                const uint64_t k = keys[q];
+                if (k != 0ull && (k & mask) == prefix) atomicAdd(&hist[(k >> (8 * pos)) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int rem = s_remaining;
+                int b = 255;
+                for (; b >= 0; --b) {
+                    if ((int)hist[b] >= rem) break;
+                    rem -= (int)hist[b];
+                }
+                s_remaining = rem;
+                s_prefix = prefix | ((uint64_t)b << (8 * pos));
+                s_mask = mask | (255ull << (8 * pos));
+            }
+            __syncthreads();
+        }
+        thr = s_prefix;  // the Wsel-th largest key (keys are unique)
+    }
+    const int count = nnz < Wsel ? nnz : Wsel;
+    for (int64_t q = tid; q < N; q += SEL_THREADS) {
+        const uint64_t k = keys[q];
+        if (k != 0ull && k >= thr) {
+            const int slot = atomicAdd(&s_count, 1);
+            if (slot < SEL_MAX) sel[slot] = k;
+        }
+    }
+    __syncthreads();
+    int n2 = 1;
+    while (n2 < count) n2 <<= 1;
+    for (int q = count + tid; q < n2; q += SEL_THREADS) sel[q] = 0ull;
+    __syncthreads();
+    // sort by the order word: larger low word = earlier path order
+    for (int size = 2; size <= n2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = tid; q < (n2 >> 1); q += SEL_THREADS) {
+                const int lo = 2 * stride * (q / stride) + (q % stride);
+                const int hi = lo + stride;
+                const uint64_t a = sel[lo], b = sel[hi];
+                const uint32_t la = (uint32_t)a, lb = (uint32_t)b;
+                const bool desc = (lo & size) == 0;
+                if (desc ? (la < lb) : (la > lb)) {
+                    sel[lo] = b;
+                    sel[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = tid; r < count; r += SEL_THREADS) {
+        const uint64_t k = sel[r];
+        const uint32_t order = 0xFFFFFFFFu - (uint32_t)k;
+        Surv s;
+        s.parent = first ? 0 : (int32_t)(order / (uint32_t)Kmul);
+        s.digit = first ? (int32_t)order : (int32_t)(order % (uint32_t)Kmul);
+        s.score = (int64_t)(k >> 32) - 1;
+        surv[r] = s;
+    }
+    if (tid == 0) *nsurv = count;
+}
+
+// rows of the surviving paths: parent row prefix plus the bits of V_i
+__global__ void k_merge_build(const MergeLevel* lv, int i, const uint32_t* cand, int K, const Surv* surv,
+                              const int32_t* nsurv, const uint32_t* prow, uint32_t* nrow, int nw, int64_t* scores,
+                              int final_out, int nV)
+{
+    const int r = blockIdx.x;
+    if (r >= *nsurv) return;
+    const MergeLevel L = lv[i];
+    const Surv s = surv[r];
+    const int end = L.start + L.size;
+    const int nwp = final_out ? nw : (end + 31) >> 5;
+    uint32_t* dst = nrow + (size_t)r * nw;
+    const bool first = (i == 0);
+    const uint32_t* src = first ? nullptr : prow + (size_t)s.parent * nw;
+    for (int q = threadIdx.x; q < nwp; q += blockDim.x) dst[q] = first ? 0u : src[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int j = first ? (s.digit >> 1) : s.digit;
+        const uint32_t b = cand[(size_t)i * K + j];
+        uint32_t o;
+        if (first) o = (uint32_t)(s.digit & 1);
+        else o = (b & 1u) ^ ((src[L.start >> 5] >> (L.start & 31)) & 1u);
+        const uint32_t bits = (b ^ (o ? 0xFFFFFFFFu : 0u)) & (L.size == 32 ? 0xFFFFFFFFu : ((1u << L.size) - 1u));
+        // place bits [start, end) : spans at most two words
+        const int w0 = L.start >> 5, sh = L.start & 31;
+        const uint64_t lm = (L.size == 32 ? 0xFFFFFFFFull : ((1ull << L.size) - 1ull)) << sh;
+        const uint64_t val = (uint64_t)bits << sh;
+        uint64_t cur = (uint64_t)dst[w0];
+        if (w0 + 1 < nw) cur |= (uint64_t)dst[w0 + 1] << 32;
+        cur = (cur & ~lm) | val;
+        dst[w0] = (uint32_t)cur;
+        if (w0 + 1 < nw && (sh + L.size) > 32) dst[w0 + 1] = (uint32_t)(cur >> 32);
+        if (final_out) {
+            // clear the bits past the last vertex
+            if (nV & 31) dst[nw - 1] &= (1u << (nV & 31)) - 1u;
+        }
+        scores[r] = s.score;
+    }
+}
+
+__global__ void k_merge_fail(uint32_t* out, int nw, int64_t* cut, const int32_t* nsurv)
+{
+    if (*nsurv > 0) return;
+    for (int q = threadIdx.x; q < nw; q += blockDim.x) out[q] = 0u;
+    if (threadIdx.x == 0) *cut = -1;
+}
+
+__global__ void k_set_count(int32_t* c, int v)
+{
+    if (threadIdx.x == 0) *c = v;
+}
+
+__global__ void k_copy_count(int32_t* c)
+{
+    if (threadIdx.x == 0) c[0] = c[1];
+}
+
+hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV, const uint32_t* cand,
+                        uint32_t* best, int64_t* best_cut, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_merge_intra, dim3(M), dim3(64), 0, s, m.lv, m.intra, cand, K, m.ccut);
+    hipLaunchKernelGGL(k_merge_first, dim3(1), dim3(128), 0, s, cand, K, m.ccut, m.keys);
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, s, m.counts, 1);
+    int cur = 0;
+    for (int i = 0; i < M; ++i) {
+        const bool last = i == M - 1;
+        const int wsel = last ? 1 : W;
+        if (i > 0)
+            hipLaunchKernelGGL(k_merge_expand, dim3(W), dim3(64), 0, s, m.lv, i, m.back, cand, K, m.ccut,
+                               m.rows[cur], nw, m.scores, m.counts, m.keys);
+        hipLaunchKernelGGL(k_merge_select, dim3(1), dim3(SEL_THREADS), 0, s, m.keys, m.counts,
+                           i == 0 ? 2 * K : K, wsel, i == 0 ? 1 : 0, m.surv, m.counts + 1);
+        uint32_t* dst = last ? best : m.rows[cur ^ 1];
+        hipLaunchKernelGGL(k_merge_build, dim3(last ? 1 : W), dim3(64), 0, s, m.lv, i, cand, K, m.surv,
+                           m.counts + 1, m.rows[cur], dst, nw, last ? best_cut : m.scores, last ? 1 : 0, nV);
+        if (last) {
+            hipLaunchKernelGGL(k_merge_fail, dim3(1), dim3(64), 0, s, best, nw, best_cut, m.counts + 1);
+        } else {
+            // survivors become the current paths
+            hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, m.counts);
+        }
+        cur ^= 1;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pq

@@ -1,0 +1,177 @@
+"""The plain ParaQAOA method on one GPU (paper Sec. 3, Fig. 3 stages 1-3):
+partition (host), batched QAOA with on-device angle optimisation, top-k,
+level-wise merge and integer cut evaluation. Every numeric step runs in
+libparaqaoa's HIP kernels; this module only orders the calls and owns the
+torch tensors that hold device memory."""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi
+from .batch import QaoaBatch, _ptr, _stream
+from .partition import Partition, bucket_edges
+
+
+@dataclass
+class SolveConfig:
+    p: int = 3
+    iters: int = 50            # Adam steps per subgraph
+    k: int = 16                # top-k per subgraph
+    beam: int = 4096           # merge beam width W
+    lr: float = 0.05
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+
+def cold_start(p: int, B: int):
+    """Linear-ramp angles gamma_l = (pi/2)(l - 1/2)/p, beta_l = (pi/4)(1 - (l - 1/2)/p)
+    for every subgraph (our reading: the paper gives no initialisation)."""
+    f = (np.arange(p) + 0.5) / p
+    g = np.tile(0.5 * math.pi * f, (B, 1))
+    b = np.tile(0.25 * math.pi * (1.0 - f), (B, 1))
+    return g, b
+
+
+@dataclass
+class SolveResult:
+    cut: int
+    assignment: np.ndarray          # uint8 per vertex
+    energies: np.ndarray            # final <C> per subgraph
+    gamma: np.ndarray
+    beta: np.ndarray
+    cand: np.ndarray                # uint32 [M, k]
+    timings: dict = field(default_factory=dict)
+
+
+class Solver:
+    """Holds the device buffers of one graph so repeated solves allocate
+    nothing new (the bench times `run`)."""
+
+    def __init__(self, graph, part: Partition, cfg: SolveConfig, device="cuda"):
+        self.g = graph
+        self.part = part
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.sub_edges, self.inter = bucket_edges(part, graph.u, graph.v, graph.w)
+        self.B = part.M
+        dev = self.device
+        self.batch = QaoaBatch(part.size, self.sub_edges, max_p=cfg.p, max_k=cfg.k, gradient=True, device=dev)
+        P = self.B * cfg.p
+        self.theta = torch.zeros(2 * P, dtype=torch.float64, device=dev)   # [gamma | beta]
+        self.grad = torch.zeros(2 * P, dtype=torch.float64, device=dev)    # [dgamma | dbeta]
+        self.m = torch.zeros(2 * P, dtype=torch.float64, device=dev)
+        self.v = torch.zeros(2 * P, dtype=torch.float64, device=dev)
+        self.step = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.E = torch.zeros(self.B, dtype=torch.float64, device=dev)
+        self.idx = torch.zeros(self.B * cfg.k, dtype=torch.int32, device=dev)
+        self.prob = torch.zeros(self.B * cfg.k, dtype=torch.float32, device=dev)
+        # full graph on the device for the final CutVal
+        self.du = torch.as_tensor(graph.u, device=dev)
+        self.dv = torch.as_tensor(graph.v, device=dev)
+        self.dw = torch.as_tensor(graph.w, device=dev)
+        self.nw = (graph.num_vertices + 31) // 32
+        self.best = torch.zeros(self.nw, dtype=torch.int32, device=dev)
+        self.best_cut = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.eval_cut = torch.zeros(1, dtype=torch.int64, device=dev)
+        mb = _abi.qaoa_merge_workspace_bytes(graph.num_vertices, part.M, graph.num_edges, cfg.k, cfg.beam)
+        self.merge_ws = torch.empty(mb, dtype=torch.uint8, device=dev)
+
+    def rebuild(self, stream=None):
+        """Re-create the batch on its existing workspace: validates the
+        subgraphs again, uploads the edge lists and rebuilds every cut table
+        (the batch-build step of the hot path)."""
+        bt = self.batch
+        from .partition import batch_arrays
+        nq, off, u, v, w = batch_arrays(self.part.size, self.sub_edges)
+        _abi.qaoa_batch_destroy(bt.handle)
+        bt.handle = 0
+        flags = _abi.QAOA_FLAG_GRADIENT
+        bt.handle = _abi.qaoa_batch_create(bt.B, nq, off, u, v, w, bt.max_p, bt.max_k, flags,
+                                           _ptr(bt.workspace), bt.workspace.numel(), _stream(stream))
+
+    def set_angles(self, gamma, beta):
+        P = self.B * self.cfg.p
+        self.theta[:P] = torch.as_tensor(np.asarray(gamma).reshape(-1), dtype=torch.float64)
+        self.theta[P:] = torch.as_tensor(np.asarray(beta).reshape(-1), dtype=torch.float64)
+        self.m.zero_()
+        self.v.zero_()
+        self.step.zero_()
+
+    def optimise(self, iters: int, stream=None):
+        """`iters` Adam ascent steps on every subgraph's <C> (no host sync)."""
+        cfg = self.cfg
+        P = self.B * cfg.p
+        s = _stream(stream)
+        th, gr = _ptr(self.theta), _ptr(self.grad)
+        for _ in range(iters):
+            _abi.qaoa_expectation_grad(self.batch.handle, cfg.p, th, th + 8 * P, _ptr(self.E), gr, gr + 8 * P, s)
+            _abi.qaoa_adam_step(2 * P, th, gr, _ptr(self.m), _ptr(self.v), _ptr(self.step), cfg.lr, cfg.beta1,
+                                cfg.beta2, cfg.eps, 1, s)
+
+    def finish(self, stream=None):
+        """Final state, expectation, top-k, merge and CutVal (device only)."""
+        cfg = self.cfg
+        P = self.B * cfg.p
+        s = _stream(stream)
+        th = _ptr(self.theta)
+        _abi.qaoa_apply_layers(self.batch.handle, cfg.p, th, th + 8 * P, s)
+        _abi.qaoa_expectation(self.batch.handle, _ptr(self.E), s)
+        _abi.qaoa_topk(self.batch.handle, cfg.k, _ptr(self.idx), _ptr(self.prob), s)
+        g = self.g
+        _abi.qaoa_merge_beam(g.num_vertices, self.part.M, self.part.start, self.part.size, g.num_edges, g.u, g.v,
+                             g.w, cfg.k, _ptr(self.idx), cfg.beam, _ptr(self.merge_ws), self.merge_ws.numel(),
+                             _ptr(self.best), _ptr(self.best_cut), s)
+        _abi.maxcut_eval(g.num_vertices, g.num_edges, _ptr(self.du), _ptr(self.dv), _ptr(self.dw), 1,
+                         _ptr(self.best), _ptr(self.eval_cut), s)
+
+    def run(self, gamma0=None, beta0=None, iters=None, stream=None):
+        if gamma0 is None:
+            gamma0, beta0 = cold_start(self.cfg.p, self.B)
+        self.set_angles(gamma0, beta0)
+        self.optimise(self.cfg.iters if iters is None else iters, stream)
+        self.finish(stream)
+
+    def result(self) -> SolveResult:
+        torch.cuda.synchronize()
+        P = self.B * self.cfg.p
+        th = self.theta.cpu().numpy()
+        words = self.best.cpu().numpy().view(np.uint32)
+        nV = self.g.num_vertices
+        x = ((words[np.arange(nV) // 32] >> (np.arange(nV) % 32).astype(np.uint32)) & 1).astype(np.uint8)
+        cut = int(self.eval_cut.cpu()[0])
+        assert cut == int(self.best_cut.cpu()[0]), "merge score and CutVal disagree"
+        return SolveResult(cut=cut, assignment=x, energies=self.E.cpu().numpy(),
+                           gamma=th[:P].reshape(self.B, -1), beta=th[P:].reshape(self.B, -1),
+                           cand=self.idx.cpu().numpy().view(np.uint32).reshape(self.B, -1))
+
+    def close(self):
+        self.batch.close()
+
+
+def merge_beam(graph, part: Partition, cand: torch.Tensor, K: int, W: int, stream=None):
+    """GPU beam merge of candidates cand (int32/uint32 [M, K] on the device);
+    returns (best_words int32 tensor, best_cut int64 tensor)."""
+    dev = cand.device
+    nw = (graph.num_vertices + 31) // 32
+    mb = _abi.qaoa_merge_workspace_bytes(graph.num_vertices, part.M, graph.num_edges, K, W)
+    ws = torch.empty(mb, dtype=torch.uint8, device=dev)
+    best = torch.zeros(nw, dtype=torch.int32, device=dev)
+    cut = torch.zeros(1, dtype=torch.int64, device=dev)
+    _abi.qaoa_merge_beam(graph.num_vertices, part.M, part.start, part.size, graph.num_edges, graph.u, graph.v,
+                         graph.w, K, _ptr(cand), W, _ptr(ws), mb, _ptr(best), _ptr(cut), _stream(stream))
+    return best, cut, ws
+
+
+def maxcut_eval(graph_dev, num_vertices, assign: torch.Tensor, stream=None):
+    """CutVal of each row of `assign` (int32 [A, ceil(V/32)] device)."""
+    du, dv, dw = graph_dev
+    A = assign.shape[0]
+    out = torch.empty(A, dtype=torch.int64, device=assign.device)
+    _abi.maxcut_eval(num_vertices, du.numel(), _ptr(du), _ptr(dv), _ptr(dw), A, _ptr(assign), _ptr(out),
+                     _stream(stream))
+    return out

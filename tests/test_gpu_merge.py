@@ -1,0 +1,157 @@
+"""GPU parity of maxcut_eval and the beam merge (bit-exact against the oracle
+given the same candidates), and of the plain solve pipeline."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_26232_amd import synth, _abi
+from paper_2603_26232_amd.partition import partition_equal, partition_chain, bucket_edges
+from paper_2603_26232_amd.solve import Solver, SolveConfig, merge_beam, maxcut_eval, cold_start
+
+pytestmark = pytest.mark.gpu
+
+
+def _words(x):
+    nV = x.shape[0]
+    w = np.zeros((nV + 31) // 32, dtype=np.uint32)
+    for t in np.nonzero(x)[0]:
+        w[t // 32] |= np.uint32(1 << (t % 32))
+    return w
+
+
+def _unpack(words, nV):
+    words = np.asarray(words).view(np.uint32)
+    return ((words[np.arange(nV) // 32] >> (np.arange(nV) % 32).astype(np.uint32)) & 1).astype(np.uint8)
+
+
+@pytest.mark.parametrize("nV,p,A,weighted", [(1, 0.0, 1, False), (33, 0.3, 17, True), (400, 0.05, 64, False),
+                                             (2000, 0.01, 5, True)])
+def test_maxcut_eval(nV, p, A, weighted):
+    g = synth.erdos_renyi(nV, p, 3) if nV > 1 else synth.Graph(1, [], [])
+    w = synth.random_weights(g.num_edges, 5) if weighted else g.w
+    rng = np.random.default_rng(nV)
+    X = rng.integers(0, 2, (A, nV)).astype(np.uint8)
+    words = np.stack([_words(x) for x in X])
+    ref = oracle.cutval_packed(nV, g.u, g.v, w, words)
+    dev = (torch.as_tensor(g.u, device="cuda"), torch.as_tensor(g.v, device="cuda"), torch.as_tensor(w, device="cuda"))
+    got = maxcut_eval(dev, nV, torch.as_tensor(words.view(np.int32), device="cuda")).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_maxcut_eval_flags_bad_edge_ids():
+    u = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    v = torch.tensor([1, 9], dtype=torch.int32, device="cuda")
+    w = torch.ones(2, dtype=torch.int32, device="cuda")
+    assign = torch.zeros((2, 1), dtype=torch.int32, device="cuda")
+    got = maxcut_eval((u, v, w), 4, assign).cpu().numpy()
+    assert np.all(got == -1)
+
+
+def _instance(seed, nV, N, K, raw=False, p_edge=0.1, weighted=False, ragged=False):
+    g = synth.erdos_renyi(nV, p_edge, seed)
+    w = synth.random_weights(g.num_edges, seed + 1, 1, 4) if weighted else g.w
+    g = synth.Graph(nV, g.u, g.v, w)
+    if ragged:
+        part = partition_chain(nV, synth.ragged_sizes(seed + 1, 3, N, 4 * nV))
+    else:
+        part = partition_equal(nV, N)
+    rng = np.random.default_rng(seed)
+    cand = np.full((part.M, K), 0xFFFFFFFF, dtype=np.uint32)
+    for i in range(part.M):
+        pool = np.arange(0, 1 << int(part.size[i]), 1 if raw else 2, dtype=np.int64)
+        kk = min(K, pool.size)
+        cand[i, :kk] = rng.choice(pool, kk, replace=False)
+    return g, part, cand
+
+
+@pytest.mark.parametrize("seed,nV,N,K,W,raw,weighted,ragged", [
+    (0, 9, 4, 2, 4096, False, False, False),   # exact: W >= 2 K^(M-1)
+    (1, 13, 5, 3, 4096, True, True, False),     # exact, raw candidates
+    (2, 60, 8, 4, 16, False, False, False),     # narrow beam
+    (3, 120, 10, 16, 64, False, True, True),    # ragged chain, padding rows
+    (4, 400, 20, 16, 4096, False, False, False),  # the 400-vertex shape
+    (5, 7, 7, 8, 3, False, False, False),       # a single subgraph
+    (6, 300, 12, 5, 1, True, True, False),      # W = 1 (greedy)
+])
+def test_merge_matches_oracle(seed, nV, N, K, W, raw, weighted, ragged):
+    g, part, cand = _instance(seed, nV, N, K, raw=raw, weighted=weighted, ragged=ragged)
+    best, cut, _ = merge_beam(g, part, torch.as_tensor(cand.view(np.int32), device="cuda"), K, W)
+    ref_cut, ref_x, digits, _ = oracle.merge(nV, part.start, part.size, g.u, g.v, g.w, cand, W=W)
+    got_x = _unpack(best.cpu().numpy(), nV)
+    assert int(cut.cpu()[0]) == ref_cut
+    assert np.array_equal(got_x, ref_x)
+    assert oracle.cutval(g.u, g.v, g.w, got_x) == ref_cut
+    if W >= 2 * K ** (part.M - 1):
+        ex = oracle.merge(nV, part.start, part.size, g.u, g.v, g.w, cand, W=0)
+        assert ex[0] == ref_cut and np.array_equal(ex[1], got_x)
+
+
+def test_merge_rejects_bad_chains():
+    g = synth.erdos_renyi(10, 0.3, 0)
+    cand = torch.zeros((2, 2), dtype=torch.int32, device="cuda")
+    from paper_2603_26232_amd.partition import Partition
+    bad = Partition(10, [0, 5], [5, 5])  # no shared vertex
+    with pytest.raises(_abi.QaoaError):
+        merge_beam(g, bad, cand, 2, 4)
+
+
+def _first_gradient_check(solver, part, sub_edges, p, which):
+    g0, b0 = cold_start(p, part.M)
+    E, dg, db = solver.batch.expectation_grad(g0, b0)
+    E, dg, db = E.cpu().numpy(), dg.cpu().numpy(), db.cpu().numpy()
+    for b in which:
+        u, v, w = sub_edges[b]
+        n = int(part.size[b])
+        C = oracle.cut_table(n, u, v, w)
+        e_ref, g_ref, b_ref = oracle.gradient(n, C, g0[b], b0[b])
+        scale = max(1.0, float(np.abs(np.concatenate([g_ref, b_ref])).max()))
+        assert abs(E[b] - e_ref) <= 1e-5 * max(1.0, e_ref)
+        assert np.max(np.abs(dg[b] - g_ref)) <= 1e-4 * scale
+        assert np.max(np.abs(db[b] - b_ref)) <= 1e-4 * scale
+
+
+def test_plain_solve_small_end_to_end():
+    g = synth.erdos_renyi(57, 0.15, 21)
+    part = partition_equal(57, 8)
+    cfg = SolveConfig(p=2, iters=15, k=4, beam=64)
+    S = Solver(g, part, cfg)
+    _first_gradient_check(S, part, S.sub_edges, cfg.p, range(part.M))
+    S.run()
+    r = S.result()
+    # optimiser trajectory vs the FP64 oracle's Adam from the same start
+    g0, b0 = cold_start(cfg.p, part.M)
+    og, ob, oE, oidx, oprob = oracle.solve_batch(part.size, S.sub_edges, g0, b0, cfg.iters, cfg.k, lr=cfg.lr)
+    assert np.max(np.abs(r.gamma - og)) <= 1e-4 and np.max(np.abs(r.beta - ob)) <= 1e-4
+    assert np.max(np.abs(r.energies - oE) / np.maximum(1, oE)) <= 1e-5
+    # merge and CutVal bit-exact given the GPU's candidates
+    ref_cut, ref_x, _, _ = oracle.merge(57, part.start, part.size, g.u, g.v, g.w, r.cand, W=cfg.beam)
+    assert r.cut == ref_cut and np.array_equal(r.assignment, ref_x)
+    assert oracle.cutval(g.u, g.v, g.w, r.assignment) == r.cut
+    S.close()
+
+
+def test_plain_solve_400_vertices_full_size():
+    """The 400-vertex plain-method workload at its full size: G(400, 0.05),
+    21 subgraphs of 20 qubits, p = 3, 50 Adam steps, top-16, beam 4096."""
+    g = synth.erdos_renyi(400, 0.05, 0)
+    part = partition_equal(400, 20)
+    cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
+    S = Solver(g, part, cfg)
+    _first_gradient_check(S, part, S.sub_edges, cfg.p, [0, 7])
+    S.run()
+    r = S.result()
+    # final states of sampled subgraphs at the GPU's final angles
+    from test_gpu_sim import _accept_topk
+    for b in [3, 20]:
+        u, v, w = S.sub_edges[b]
+        C = oracle.cut_table(20, u, v, w)
+        psi = oracle.qaoa_state(20, C, r.gamma[b], r.beta[b])
+        st = S.batch.state(b).cpu().numpy()
+        assert np.max(np.abs(st - psi)) <= 1e-5
+        e_ref = oracle.expectation(20, psi, C)
+        assert abs(r.energies[b] - e_ref) <= 1e-5 * max(1.0, e_ref)
+        _accept_topk(r.cand[b], S.prob.view(part.M, -1)[b].cpu().numpy(), psi, cfg.k)
+    ref_cut, ref_x, _, _ = oracle.merge(400, part.start, part.size, g.u, g.v, g.w, r.cand, W=cfg.beam)
+    assert r.cut == ref_cut and np.array_equal(r.assignment, ref_x)
+    S.close()

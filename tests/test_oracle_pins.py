@@ -454,8 +454,9 @@ def test_beam_with_full_width_equals_exhaustive(seed, M, K, n_sub):
     bm = oracle.merge(nV, start, size, g.u, g.v, None, cand, W=2 * K ** (M - 1))
     assert ex[0] == bm[0] and np.array_equal(ex[1], bm[1]) and np.array_equal(ex[2], bm[2])
     # a narrow beam can only do as well or worse, and its cut is consistent
-    nb = oracle.merge(nV, start, size, g.u, g.v, None, cand, W=2)
-    assert nb[0] <= ex[0] and oracle.cutval(g.u, g.v, None, nb[1]) == nb[0]
+    for narrow in (1, 2):
+        nb = oracle.merge(nV, start, size, g.u, g.v, None, cand, W=narrow)
+        assert nb[0] <= ex[0] and oracle.cutval(g.u, g.v, None, nb[1]) == nb[0]
 
 
 def test_start_path_counts_from_paper():
