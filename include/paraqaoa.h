@@ -65,6 +65,11 @@ typedef void* qaoa_stream_t;
 /* create flags */
 #define QAOA_FLAG_GRADIENT 0x1u /* reserve the adjoint state; enables qaoa_expectation_grad */
 #define QAOA_FLAG_TOPK_RAW 0x2u /* top-k over all z; default: only z with bit 0 clear */
+/* Do not simulate subgraphs without edges: their state is e^{-i n sum beta}|+>^n,
+ * so <C> = 0, the gradient is 0 and every bitstring is equally likely (top-k =
+ * the k smallest candidate indices, probability 2^-n). Their states are not
+ * stored (qaoa_state_offset reports QAOA_ERR_STATE for them). */
+#define QAOA_FLAG_SKIP_EDGELESS 0x4u
 
 /* Workspace size for a batch (paper Sec. 3.3: the subgraphs {G[V_i]} that
  * Alg. 1 produces, each solved by its own QAOA instance).
@@ -201,6 +206,31 @@ qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const int32_t* h_
                               int32_t K, const uint32_t* d_cand, int32_t W, void* d_workspace,
                               size_t workspace_bytes, uint32_t* d_best_assign, int64_t* d_best_cut,
                               qaoa_stream_t stream);
+
+/* Angle predictor for a learned warm start of the angle optimisation (not a
+ * step of the paper; Sec. 2.2 notes that initialisation affects solution
+ * quality and iteration count). A multilayer perceptron in -> hidden ->
+ * hidden -> out, ReLU hidden layers, linear output. Parameters are one flat
+ * FP64 array, row-major: W1[hidden][in], b1[hidden], W2[hidden][hidden],
+ * b2[hidden], W3[out][hidden], b3[out] (qaoa_mlp_num_params gives its
+ * length). Arithmetic is FP32 with FP64 gradient sums; limits in <= 64,
+ * hidden <= 256, out <= 64.
+ *   qaoa_mlp_forward:  d_x float [batch][in] -> d_y float [batch][out];
+ *                      d_act float [batch][2*hidden] keeps both hidden
+ *                      activations for the backward pass
+ *   qaoa_mlp_backward: loss = mean over batch and outputs of (y - t)^2 into
+ *                      d_loss double [1], its gradient into d_grad double
+ *                      [num_params]; d_y/d_act from the forward call on the
+ *                      same parameters and inputs; d_scratch device bytes of
+ *                      at least qaoa_mlp_scratch_bytes */
+qaoa_status_t qaoa_mlp_num_params(int32_t in_dim, int32_t hidden, int32_t out_dim, int64_t* out);
+qaoa_status_t qaoa_mlp_scratch_bytes(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim, size_t* out);
+qaoa_status_t qaoa_mlp_forward(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim, const double* d_params,
+                               const float* d_x, float* d_y, float* d_act, qaoa_stream_t stream);
+qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                const double* d_params, const float* d_x, const float* d_y, const float* d_act,
+                                const float* d_target, void* d_scratch, size_t scratch_bytes, double* d_grad,
+                                double* d_loss, qaoa_stream_t stream);
 
 /* Where subgraph b's state lives: the byte offset, inside the workspace, of
  * its 2^n complex64 amplitudes (interleaved real, imaginary; index z). After

@@ -90,6 +90,12 @@ def _declare(L):
     L.or_partition_equal.argtypes = [ct.c_int32, ct.c_int32, _i32p, _i32p]
     L.or_partition_chain.restype = ct.c_int32
     L.or_partition_chain.argtypes = [ct.c_int32, ct.c_int32, _i32p, _i32p, _i32p]
+    L.or_mlp_num_params.restype = ct.c_int64
+    L.or_mlp_num_params.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32]
+    L.or_mlp_forward.restype = None
+    L.or_mlp_forward.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, _f64p, _f64p, _f64p]
+    L.or_mlp_loss_grad.restype = ct.c_double
+    L.or_mlp_loss_grad.argtypes = [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, _f64p, _f64p, _f64p, _f64p]
     L.or_merge.restype = ct.c_int64
     L.or_merge.argtypes = [ct.c_int32, ct.c_int32, _i32p, _i32p, ct.c_int64, _i32p, _i32p,
                            ct.c_void_p, ct.c_int32, _u32p, ct.c_int64, _u8p, _i32p,
@@ -313,3 +319,30 @@ def merge(num_vertices, start, size, u, v, w, cand, W=0):
     if best < 0:
         raise ValueError("invalid merge input")
     return int(best), x, digits, leaves.value
+
+
+# --- angle predictor (learned warm start) ------------------------------------
+def mlp_num_params(in_dim, hidden, out_dim) -> int:
+    return int(lib().or_mlp_num_params(in_dim, hidden, out_dim))
+
+
+def mlp_forward(params, X, hidden, out_dim):
+    """FP64 MLP forward: X [B, in] -> Y [B, out]."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    B, in_dim = X.shape
+    Y = np.zeros((B, out_dim), dtype=np.float64)
+    lib().or_mlp_forward(B, in_dim, hidden, out_dim, np.ascontiguousarray(params, dtype=np.float64),
+                         X.reshape(-1), Y.reshape(-1))
+    return Y
+
+
+def mlp_loss_grad(params, X, T, hidden):
+    """(mean squared error, gradient) of the MLP on (X, T)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    B, in_dim = X.shape
+    out_dim = T.shape[1]
+    G = np.zeros(mlp_num_params(in_dim, hidden, out_dim), dtype=np.float64)
+    loss = lib().or_mlp_loss_grad(B, in_dim, hidden, out_dim, np.ascontiguousarray(params, dtype=np.float64),
+                                  X.reshape(-1), T.reshape(-1), G)
+    return float(loss), G

@@ -640,3 +640,114 @@ int64_t or_merge(int32_t nV, int32_t M, const int32_t* start, const int32_t* siz
     free(lvl_of);
     return best;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Angle predictor (not in the paper; a learned warm start for the angle     */
+/* optimisation whose initialisation Sec. 2.2 says matters): a multilayer    */
+/* perceptron in -> H -> H -> out with ReLU hidden layers and a linear       */
+/* output. Parameters, flat, row-major: W1[H][in], b1[H], W2[H][H], b2[H],   */
+/* W3[out][H], b3[out]. Loss = mean over batch and outputs of (y - t)^2.     */
+/* FP64 throughout. Pinned by central finite differences.                    */
+/* ------------------------------------------------------------------------ */
+int64_t or_mlp_num_params(int32_t in, int32_t H, int32_t out)
+{
+    return (int64_t)H * in + H + (int64_t)H * H + H + (int64_t)out * H + out;
+}
+
+static void mlp_one(int32_t in, int32_t H, int32_t out, const double* P, const double* x, double* h1, double* h2,
+                    double* y)
+{
+    const double* W1 = P;
+    const double* b1 = W1 + (int64_t)H * in;
+    const double* W2 = b1 + H;
+    const double* b2 = W2 + (int64_t)H * H;
+    const double* W3 = b2 + H;
+    const double* b3 = W3 + (int64_t)out * H;
+    for (int32_t i = 0; i < H; ++i) {
+        double a = b1[i];
+        for (int32_t f = 0; f < in; ++f) a += W1[(int64_t)i * in + f] * x[f];
+        h1[i] = a > 0.0 ? a : 0.0;
+    }
+    for (int32_t i = 0; i < H; ++i) {
+        double a = b2[i];
+        for (int32_t j = 0; j < H; ++j) a += W2[(int64_t)i * H + j] * h1[j];
+        h2[i] = a > 0.0 ? a : 0.0;
+    }
+    for (int32_t o = 0; o < out; ++o) {
+        double a = b3[o];
+        for (int32_t j = 0; j < H; ++j) a += W3[(int64_t)o * H + j] * h2[j];
+        y[o] = a;
+    }
+}
+
+void or_mlp_forward(int32_t B, int32_t in, int32_t H, int32_t out, const double* P, const double* X, double* Y)
+{
+    double* h1 = (double*)malloc((size_t)H * sizeof(double));
+    double* h2 = (double*)malloc((size_t)H * sizeof(double));
+    for (int32_t s = 0; s < B; ++s) mlp_one(in, H, out, P, X + (int64_t)s * in, h1, h2, Y + (int64_t)s * out);
+    free(h1);
+    free(h2);
+}
+
+/* loss and its gradient with respect to every parameter (back-propagation) */
+double or_mlp_loss_grad(int32_t B, int32_t in, int32_t H, int32_t out, const double* P, const double* X,
+                        const double* T, double* G)
+{
+    int64_t np = or_mlp_num_params(in, H, out);
+    for (int64_t i = 0; i < np; ++i) G[i] = 0.0;
+    const double* W2 = P + (int64_t)H * in + H;
+    const double* W3 = W2 + (int64_t)H * H + H;
+    double* gW1 = G;
+    double* gb1 = gW1 + (int64_t)H * in;
+    double* gW2 = gb1 + H;
+    double* gb2 = gW2 + (int64_t)H * H;
+    double* gW3 = gb2 + H;
+    double* gb3 = gW3 + (int64_t)out * H;
+    double* h1 = (double*)malloc((size_t)H * sizeof(double));
+    double* h2 = (double*)malloc((size_t)H * sizeof(double));
+    double* y = (double*)malloc((size_t)out * sizeof(double));
+    double* d3 = (double*)malloc((size_t)out * sizeof(double));
+    double* d2 = (double*)malloc((size_t)H * sizeof(double));
+    double* d1 = (double*)malloc((size_t)H * sizeof(double));
+    double loss = 0.0;
+    const double scale = 1.0 / ((double)B * (double)out);
+    for (int32_t s = 0; s < B; ++s) {
+        const double* x = X + (int64_t)s * in;
+        const double* t = T + (int64_t)s * out;
+        mlp_one(in, H, out, P, x, h1, h2, y);
+        for (int32_t o = 0; o < out; ++o) {
+            double r = y[o] - t[o];
+            loss += r * r * scale;
+            d3[o] = 2.0 * r * scale;
+        }
+        for (int32_t j = 0; j < H; ++j) {
+            double a = 0.0;
+            for (int32_t o = 0; o < out; ++o) a += W3[(int64_t)o * H + j] * d3[o];
+            d2[j] = h2[j] > 0.0 ? a : 0.0;
+        }
+        for (int32_t j = 0; j < H; ++j) {
+            double a = 0.0;
+            for (int32_t i = 0; i < H; ++i) a += W2[(int64_t)i * H + j] * d2[i];
+            d1[j] = h1[j] > 0.0 ? a : 0.0;
+        }
+        for (int32_t o = 0; o < out; ++o) {
+            for (int32_t j = 0; j < H; ++j) gW3[(int64_t)o * H + j] += d3[o] * h2[j];
+            gb3[o] += d3[o];
+        }
+        for (int32_t i = 0; i < H; ++i) {
+            for (int32_t j = 0; j < H; ++j) gW2[(int64_t)i * H + j] += d2[i] * h1[j];
+            gb2[i] += d2[i];
+        }
+        for (int32_t i = 0; i < H; ++i) {
+            for (int32_t f = 0; f < in; ++f) gW1[(int64_t)i * in + f] += d1[i] * x[f];
+            gb1[i] += d1[i];
+        }
+    }
+    free(h1);
+    free(h2);
+    free(y);
+    free(d3);
+    free(d2);
+    free(d1);
+    return loss;
+}

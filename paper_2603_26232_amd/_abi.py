@@ -18,6 +18,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "paraqaoa.h")
 
 QAOA_FLAG_GRADIENT = 0x1
 QAOA_FLAG_TOPK_RAW = 0x2
+QAOA_FLAG_SKIP_EDGELESS = 0x4
 QAOA_MAX_QUBITS = 30
 QAOA_MAX_DEPTH = 32
 QAOA_MAX_K = 64
@@ -67,8 +68,10 @@ def lib() -> ct.CDLL:
             "qaoa_merge_workspace_bytes": [_i32, _i32, _i64, _i32, _i32, _vp],
             "qaoa_merge_beam": [_i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp,
                                 ct.c_size_t, _vp, _vp, _vp],
-            "qaoa_mlp_forward": [_i32, _vp, _vp, _vp, _vp, _vp],
-            "qaoa_mlp_backward": [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+            "qaoa_mlp_num_params": [_i32, _i32, _i32, _vp],
+            "qaoa_mlp_scratch_bytes": [_i32, _i32, _i32, _i32, _vp],
+            "qaoa_mlp_forward": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
+            "qaoa_mlp_backward": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ct.c_size_t, _vp, _vp, _vp],
             "qaoa_state_offset": [_vp, _i32, _vp],
             "qaoa_profile_enable": [_i32],
             "qaoa_profile_read": [ct.c_char_p, _vp, _vp, _vp],
@@ -190,14 +193,27 @@ def qaoa_merge_beam(num_vertices, M, h_start, h_size, num_edges, h_u, h_v, h_w, 
           _vp(d_best_assign), _vp(d_best_cut), _vp(stream))
 
 
-def qaoa_mlp_forward(batch: int, d_params: int, d_x: int, d_out: int, d_act: int, stream: int) -> None:
-    _call("qaoa_mlp_forward", batch, _vp(d_params), _vp(d_x), _vp(d_out), _vp(d_act), _vp(stream))
+def qaoa_mlp_num_params(in_dim: int, hidden: int, out_dim: int) -> int:
+    out = ct.c_int64(0)
+    _call("qaoa_mlp_num_params", in_dim, hidden, out_dim, ct.byref(out))
+    return int(out.value)
 
 
-def qaoa_mlp_backward(batch: int, d_params: int, d_x: int, d_act: int, d_target: int, d_grad: int,
-                      d_loss: int, stream: int) -> None:
-    _call("qaoa_mlp_backward", batch, _vp(d_params), _vp(d_x), _vp(d_act), _vp(d_target), _vp(d_grad),
-          _vp(d_loss), _vp(stream))
+def qaoa_mlp_scratch_bytes(batch: int, in_dim: int, hidden: int, out_dim: int) -> int:
+    out = ct.c_size_t(0)
+    _call("qaoa_mlp_scratch_bytes", batch, in_dim, hidden, out_dim, ct.byref(out))
+    return int(out.value)
+
+
+def qaoa_mlp_forward(batch, in_dim, hidden, out_dim, d_params, d_x, d_y, d_act, stream) -> None:
+    _call("qaoa_mlp_forward", batch, in_dim, hidden, out_dim, _vp(d_params), _vp(d_x), _vp(d_y), _vp(d_act),
+          _vp(stream))
+
+
+def qaoa_mlp_backward(batch, in_dim, hidden, out_dim, d_params, d_x, d_y, d_act, d_target, d_scratch,
+                      scratch_bytes, d_grad, d_loss, stream) -> None:
+    _call("qaoa_mlp_backward", batch, in_dim, hidden, out_dim, _vp(d_params), _vp(d_x), _vp(d_y), _vp(d_act),
+          _vp(d_target), _vp(d_scratch), scratch_bytes, _vp(d_grad), _vp(d_loss), _vp(stream))
 
 
 def qaoa_state_offset(h: int, b: int) -> int:

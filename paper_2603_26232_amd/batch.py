@@ -23,14 +23,16 @@ class QaoaBatch:
     one caller-owned workspace tensor)."""
 
     def __init__(self, sizes, sub_edges, max_p, max_k=16, gradient=False, raw_topk=False,
-                 device="cuda", stream=None):
+                 skip_edgeless=False, device="cuda", stream=None):
         nq, off, u, v, w = batch_arrays(sizes, sub_edges)
         self.B = int(nq.shape[0])
         self.sizes = nq
         self.max_p = int(max_p)
         self.max_k = int(max_k)
         self.device = torch.device(device)
-        flags = (_abi.QAOA_FLAG_GRADIENT if gradient else 0) | (_abi.QAOA_FLAG_TOPK_RAW if raw_topk else 0)
+        flags = ((_abi.QAOA_FLAG_GRADIENT if gradient else 0) | (_abi.QAOA_FLAG_TOPK_RAW if raw_topk else 0)
+                 | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0))
+        self.flags = flags
         nbytes = _abi.qaoa_workspace_bytes(self.B, nq, off, w, self.max_p, self.max_k, flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.handle = _abi.qaoa_batch_create(self.B, nq, off, u, v, w, self.max_p, self.max_k, flags,

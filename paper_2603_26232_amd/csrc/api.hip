@@ -128,14 +128,24 @@ struct Plan {
     int64_t total_edges = 0;
     int lut_max = 1;
     // region offsets
-    uint64_t o_subs = 0, o_work_all = 0, o_work_cls[MAX_GROUPS + 1] = {}, o_small = 0, o_edges = 0,
-             o_coef = 0, o_lut = 0, o_pe = 0, o_pgb = 0, o_pgg = 0, o_keys = 0, total = 0;
-    int nwork_cls[MAX_GROUPS + 1] = {};
+    uint64_t o_subs = 0, o_work_all = 0, o_small = 0, o_edges = 0, o_coef = 0, o_lut = 0, o_pe = 0, o_pgb = 0,
+             o_pgg = 0, o_keys = 0, total = 0;
     int nsmall = 0;
     // host images of the metadata regions
-    std::vector<int2> work_all, work_cls[MAX_GROUPS + 1];
+    std::vector<int2> work_all;
     std::vector<int32_t> small;
+    // subgraphs with the same group count and group shapes share one pass
+    // program and one launch per pass
+    struct Class {
+        int G;
+        int chain[MAX_GROUPS];
+        std::vector<int2> work;
+        uint64_t o_work;
+    };
+    std::vector<Class> classes;
 };
+
+int chain_of(const SubDesc& d, int g) { return g == 0 ? 3 : (d.gsize[g] >= 5 ? 2 : 1); }
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -153,7 +163,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     if (!nq || !eoff) return fail(QAOA_ERR_INVALID_ARG, "num_qubits and edge_offsets are required");
     if (max_p < 1 || max_p > MAX_P) return fail(QAOA_ERR_OUT_OF_RANGE, "max_p = %d outside 1..%d", max_p, MAX_P);
     if (max_k < 1 || max_k > MAX_K) return fail(QAOA_ERR_OUT_OF_RANGE, "max_k = %d outside 1..%d", max_k, MAX_K);
-    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW))
+    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS))
         return fail(QAOA_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if (eoff[0] != 0) return fail(QAOA_ERR_INVALID_ARG, "edge_offsets[0] = %lld must be 0", (long long)eoff[0]);
     P.B = B;
@@ -194,7 +204,8 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
             }
         }
         d.lut_len = (int32_t)wsum + 1;
-        d.ntiles = n > TILE_BITS ? (1 << (n - TILE_BITS)) : 1;
+        d.skip = (flags & QAOA_FLAG_SKIP_EDGELESS) && eoff[b + 1] == eoff[b];
+        d.ntiles = d.skip ? 0 : (n > TILE_BITS ? (1 << (n - TILE_BITS)) : 1);
         d.tile_base = (int32_t)tiles;
         d.nedges = (int32_t)(eoff[b + 1] - eoff[b]);
         tiles += d.ntiles;
@@ -208,18 +219,33 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     P.work_all.reserve(tiles);
     for (int b = 0; b < B; ++b)
         for (int t = 0; t < P.subs[b].ntiles; ++t) P.work_all.push_back(make_int2(b, t));
-    for (int G = 2; G <= MAX_GROUPS; ++G) {
-        // larger subgraphs first
+    {
+        // larger subgraphs first within each class
         std::vector<int> order;
         for (int b = 0; b < B; ++b)
-            if (P.subs[b].ngroups == G) order.push_back(b);
+            if (P.subs[b].ngroups >= 2) order.push_back(b);
         std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return P.subs[a].n > P.subs[c].n; });
-        for (int b : order)
-            for (int t = 0; t < P.subs[b].ntiles; ++t) P.work_cls[G].push_back(make_int2(b, t));
-        P.nwork_cls[G] = (int)P.work_cls[G].size();
+        for (int b : order) {
+            const SubDesc& d = P.subs[b];
+            if (d.skip) continue;
+            int ci = -1;
+            for (size_t k = 0; k < P.classes.size(); ++k) {
+                bool same = P.classes[k].G == d.ngroups;
+                for (int g = 0; same && g < d.ngroups; ++g) same = P.classes[k].chain[g] == chain_of(d, g);
+                if (same) ci = (int)k;
+            }
+            if (ci < 0) {
+                Plan::Class c{};
+                c.G = d.ngroups;
+                for (int g = 0; g < d.ngroups; ++g) c.chain[g] = chain_of(d, g);
+                P.classes.push_back(c);
+                ci = (int)P.classes.size() - 1;
+            }
+            for (int t = 0; t < d.ntiles; ++t) P.classes[ci].work.push_back(make_int2(b, t));
+        }
     }
     for (int b = 0; b < B; ++b)
-        if (P.subs[b].ngroups == 1) P.small.push_back(b);
+        if (P.subs[b].ngroups == 1 && !P.subs[b].skip) P.small.push_back(b);
     P.nsmall = (int)P.small.size();
 
     // regions
@@ -232,10 +258,10 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     };
     P.o_subs = region(sizeof(SubDesc) * B, 256);
     P.o_work_all = region(sizeof(int2) * tiles, 256);
-    for (int G = 2; G <= MAX_GROUPS; ++G) P.o_work_cls[G] = region(sizeof(int2) * P.nwork_cls[G], 256);
+    for (auto& c : P.classes) c.o_work = region(sizeof(int2) * c.work.size(), 256);
     P.o_small = region(sizeof(int32_t) * (P.nsmall + 1), 256);
     P.o_edges = region(sizeof(int32_t) * 3 * (P.total_edges + 1), 256);
-    P.o_coef = region(sizeof(float2) * B * max_p, 256);
+    P.o_coef = region(sizeof(RxCoef) * B * max_p, 256);
     uint64_t lut_total = 0;
     for (int b = 0; b < B; ++b) lut_total += (uint64_t)max_p * P.subs[b].lut_len;
     P.o_lut = region(sizeof(float2) * lut_total, 256);
@@ -247,10 +273,11 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     for (int b = 0; b < B; ++b) {
         SubDesc& d = P.subs[b];
         const uint64_t dim = 1ull << d.n;
-        d.coef = P.o_coef + sizeof(float2) * (uint64_t)b * max_p;
+        d.coef = P.o_coef + sizeof(RxCoef) * (uint64_t)b * max_p;
         d.lut = lut_o;
         lut_o += sizeof(float2) * (uint64_t)max_p * d.lut_len;
         d.edges = eo + sizeof(int32_t) * 3 * (uint64_t)eoff[b];
+        if (d.skip) continue;  // closed form, nothing stored
         d.psi = region(dim * sizeof(float2), 4096);
         d.lam = grad ? region(dim * sizeof(float2), 4096) : 0;
         d.tab = region(dim * sizeof(uint16_t), 4096);
@@ -340,7 +367,7 @@ double small_bytes(const Plan& P, int p, bool grad)
 {
     double b = 0.0;
     for (const SubDesc& d : P.subs)
-        if (d.ngroups == 1) b += (double)(1ull << d.n) * (grad ? 2.0 * (2 * p + 2) : (2.0 * (p + 1) + 8.0));
+        if (d.ngroups == 1 && !d.skip) b += (double)(1ull << d.n) * (grad ? 2.0 * (2 * p + 2) : (2.0 * (p + 1) + 8.0));
     return b;
 }
 
@@ -417,8 +444,8 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
     std::vector<uint8_t> img(meta_end, 0);
     memcpy(img.data() + P.o_subs, P.subs.data(), sizeof(SubDesc) * B);
     memcpy(img.data() + P.o_work_all, P.work_all.data(), sizeof(int2) * P.work_all.size());
-    for (int G = 2; G <= MAX_GROUPS; ++G)
-        if (P.nwork_cls[G]) memcpy(img.data() + P.o_work_cls[G], P.work_cls[G].data(), sizeof(int2) * P.nwork_cls[G]);
+    for (const auto& c : P.classes)
+        memcpy(img.data() + c.o_work, c.work.data(), sizeof(int2) * c.work.size());
     if (P.nsmall) memcpy(img.data() + P.o_small, P.small.data(), sizeof(int32_t) * P.nsmall);
     int32_t* E = (int32_t*)(img.data() + P.o_edges);
     for (int64_t e = 0; e < P.total_edges; ++e) {
@@ -446,7 +473,8 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
     h->part.total_tiles = h->P.total_tiles;
     {
         double tb = 0.0;
-        for (const SubDesc& d : h->P.subs) tb += (double)(1ull << d.n) * (d.ngroups >= 2 ? 4.0 : 2.0);
+        for (const SubDesc& d : h->P.subs)
+            if (!d.skip) tb += (double)(1ull << d.n) * (d.ngroups >= 2 ? 4.0 : 2.0);
         ProfScope ps("cut_tables", st, tb);
         hipError_t e = launch_cut_tables(ws, h->d_subs, (const int2*)(ws + h->P.o_work_all), h->P.total_tiles, st);
         if (e != hipSuccess) {
@@ -488,16 +516,16 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
         HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 0, h->part,
                              P.lut_max, st));
     }
-    for (int G = 2; G <= MAX_GROUPS; ++G) {
-        if (!P.nwork_cls[G]) continue;
-        std::vector<PassOps> passes = group_passes(forward_ops(G, p));
+    for (const auto& c : P.classes) {
+        const int2* work = (const int2*)(h->ws + c.o_work);
+        const int nw = (int)c.work.size();
+        std::vector<PassOps> passes = group_passes(forward_ops(c.G, p));
         for (size_t i = 0; i < passes.size(); ++i) {
             PassOps o = passes[i];
             o.init = i == 0;
             o.epi_e = i + 1 == passes.size();
-            ProfScope ps("fwd_pass", st, pass_bytes(o, false, P.nwork_cls[G]));
-            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_cls[G]), P.nwork_cls[G], o,
-                                    h->part, P.lut_max, st));
+            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
+            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }
     }
     h->state_valid = true;
@@ -525,7 +553,8 @@ extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, f
     hipStream_t st = (hipStream_t)stream;
     const Plan& P = h->P;
     double tk = 0.0;
-    for (const SubDesc& d : P.subs) tk += (double)(1ull << d.n) * 8.0;
+    for (const SubDesc& d : P.subs)
+        if (!d.skip) tk += (double)(1ull << d.n) * 8.0;
     ProfScope ps("topk", st, tk + 16.0 * P.total_tiles * k);
     HIP_TRY(launch_topk(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_all), P.total_tiles, P.B, k,
                         (P.flags & QAOA_FLAG_TOPK_RAW) ? 0 : 1, (uint64_t*)(h->ws + P.o_keys), nullptr, d_idx,
@@ -553,17 +582,16 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 1, h->part,
                              P.lut_max, st));
     }
-    for (int G = 2; G <= MAX_GROUPS; ++G) {
-        if (!P.nwork_cls[G]) continue;
-        const int2* work = (const int2*)(h->ws + P.o_work_cls[G]);
-        const int nw = P.nwork_cls[G];
-        std::vector<Op> ops = forward_ops(G, p);
+    for (const auto& c : P.classes) {
+        const int2* work = (const int2*)(h->ws + c.o_work);
+        const int nw = (int)c.work.size();
+        std::vector<Op> ops = forward_ops(c.G, p);
         std::vector<PassOps> fwd = group_passes(ops);
         for (size_t i = 0; i + 1 < fwd.size(); ++i) {
             PassOps o = fwd[i];
             o.init = i == 0;
             ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
-            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, o, h->part, P.lut_max, st));
+            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }
         std::vector<Op> rev(ops.rbegin(), ops.rend());
         std::vector<PassOps> bwd = group_passes(rev);
@@ -573,13 +601,13 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         f.fused = 1;
         {
             ProfScope ps("bwd_pass", st, pass_bytes(f, true, nw));
-            HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, f, h->part, P.lut_max, st));
+            HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[f.group], f, h->part, P.lut_max, st));
         }
         for (size_t i = 1; i < bwd.size(); ++i) {
             PassOps o = bwd[i];
             o.last = i + 1 == bwd.size();
             ProfScope ps("bwd_pass", st, pass_bytes(o, true, nw));
-            HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, o, h->part, P.lut_max, st));
+            HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }
     }
     {
@@ -624,6 +652,7 @@ extern "C" qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* ou
 {
     if (!h || !out_offset) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
     if (b < 0 || b >= h->P.B) return fail(QAOA_ERR_OUT_OF_RANGE, "b = %d outside 0..%d", b, h->P.B - 1);
+    if (h->P.subs[b].skip) return fail(QAOA_ERR_STATE, "subgraph %d is edgeless and was not simulated", b);
     *out_offset = (size_t)h->P.subs[b].psi;
     return ok();
 }
@@ -792,5 +821,68 @@ extern "C" qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const 
     m.scores = (int64_t*)(ws + P.o_scores);
     ProfScope ps("merge", st, 0.0);
     HIP_TRY(launch_merge(m, M, K, W, P.nw, num_vertices, d_cand, d_best_assign, d_best_cut, st));
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// angle predictor
+// ---------------------------------------------------------------------------
+static qaoa_status_t mlp_check(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim)
+{
+    if (batch < 1) return fail(QAOA_ERR_INVALID_ARG, "batch = %d", batch);
+    if (in_dim < 1 || in_dim > MLP_MAX_IN || hidden < 1 || hidden > MLP_MAX_H || out_dim < 1 || out_dim > MLP_MAX_OUT)
+        return fail(QAOA_ERR_OUT_OF_RANGE, "dims (%d, %d, %d) outside (1..%d, 1..%d, 1..%d)", in_dim, hidden, out_dim,
+                    MLP_MAX_IN, MLP_MAX_H, MLP_MAX_OUT);
+    return QAOA_OK;
+}
+
+extern "C" qaoa_status_t qaoa_mlp_num_params(int32_t in_dim, int32_t hidden, int32_t out_dim, int64_t* out)
+{
+    qaoa_status_t s = mlp_check(1, in_dim, hidden, out_dim);
+    if (s != QAOA_OK) return s;
+    if (!out) return fail(QAOA_ERR_INVALID_ARG, "out is NULL");
+    *out = mlp_num_params(MlpDims{in_dim, hidden, out_dim});
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_mlp_forward(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                          const double* d_params, const float* d_x, float* d_y, float* d_act,
+                                          qaoa_stream_t stream)
+{
+    qaoa_status_t s = mlp_check(batch, in_dim, hidden, out_dim);
+    if (s != QAOA_OK) return s;
+    if (!d_params || !d_x || !d_y || !d_act) return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("mlp_forward", st, 0.0);
+    HIP_TRY(launch_mlp_forward(batch, MlpDims{in_dim, hidden, out_dim}, d_params, d_x, d_y, d_act, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_mlp_scratch_bytes(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                                size_t* out)
+{
+    qaoa_status_t s = mlp_check(batch, in_dim, hidden, out_dim);
+    if (s != QAOA_OK) return s;
+    if (!out) return fail(QAOA_ERR_INVALID_ARG, "out is NULL");
+    *out = mlp_scratch_bytes(batch, MlpDims{in_dim, hidden, out_dim});
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                           const double* d_params, const float* d_x, const float* d_y,
+                                           const float* d_act, const float* d_target, void* d_scratch,
+                                           size_t scratch_bytes, double* d_grad, double* d_loss, qaoa_stream_t stream)
+{
+    qaoa_status_t s = mlp_check(batch, in_dim, hidden, out_dim);
+    if (s != QAOA_OK) return s;
+    if (!d_params || !d_x || !d_y || !d_act || !d_target || !d_scratch || !d_grad || !d_loss)
+        return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
+    const MlpDims d{in_dim, hidden, out_dim};
+    if (scratch_bytes < mlp_scratch_bytes(batch, d))
+        return fail(QAOA_ERR_WORKSPACE_TOO_SMALL, "scratch %zu bytes, need %zu", scratch_bytes,
+                    mlp_scratch_bytes(batch, d));
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("mlp_backward", st, 0.0);
+    HIP_TRY(launch_mlp_backward(batch, d, d_params, d_x, d_y, d_act, d_target, (float*)d_scratch, d_grad, d_loss, st));
     return ok();
 }

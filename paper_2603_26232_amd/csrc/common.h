@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/paraqaoa.h"
+
 namespace pq {
 
 // One tile = 2^12 amplitudes of one subgraph's state; a workgroup of 256
@@ -32,7 +34,8 @@ struct SubDesc {
     int32_t ntiles;   // max(1, 2^(n-12))
     int32_t tile_base;  // first global tile index
     int32_t nedges;
-    int32_t pad0, pad1;
+    int32_t skip;  // edgeless and not simulated (closed form)
+    int32_t pad1;
     uint64_t psi, lam, tab, tabB, lut, coef, edges;  // byte offsets into the workspace
 };
 
@@ -46,6 +49,20 @@ struct PassOps {
     int32_t epi_e;     // forward: write the <C> partial of each tile
     int32_t fused;     // backward: forward RX(pre) + <C> + lambda = C psi first
     int32_t last;      // backward: nothing needs storing
+};
+
+// Rotation parameters of one layer of one subgraph: e^{-i beta X} =
+// c (I - i t X) (mode 0, |cos| >= |sin|, t = tan beta) or -i s (X + i t I)
+// (mode 1, t = cot beta). Ff[g] / Fi[g] are the per-qubit factors raised to
+// the size of group g, forward (c or -i s) and inverse (c or +i s).
+struct RxCoef {
+    float2 cs;  // (cos beta, sin beta)
+    float t;
+    int32_t mode;
+    float fsq;  // |per-qubit factor|^2
+    float pad;
+    float2 Ff[MAX_GROUPS];
+    float2 Fi[MAX_GROUPS];
 };
 
 struct Partials {
@@ -88,14 +105,31 @@ hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV,
                         uint32_t* best, int64_t* best_cut, hipStream_t s);
 constexpr int MERGE_MAX_SIZE = 32;  // vertices per level (one uint32 bitstring)
 
+// ---- angle predictor (mlp.hip) ----
+constexpr int MLP_MAX_IN = 64, MLP_MAX_H = 256, MLP_MAX_OUT = 64;
+struct MlpDims {
+    int in, H, out;
+};
+int64_t mlp_num_params(const MlpDims& d);
+// scratch for the backward pass: floats [B * (2H + out)] then doubles [B]
+inline size_t mlp_scratch_bytes(int B, const MlpDims& d)
+{
+    return sizeof(float) * ((size_t)B * (2 * d.H + d.out) + 2) + sizeof(double) * (size_t)B + 8;
+}
+hipError_t launch_mlp_forward(int B, MlpDims d, const double* P, const float* X, float* Y, float* act, hipStream_t s);
+hipError_t launch_mlp_backward(int B, MlpDims d, const double* P, const float* X, const float* Y, const float* act,
+                               const float* T, float* scratch, double* G, double* loss, hipStream_t s);
+
 // ---- launchers (sim.hip) ----
 hipError_t launch_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
                              hipStream_t s);
 hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, const double* gamma,
                              const double* beta, hipStream_t s);
-hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
+// chain: layout-chain shape of the pass's group (3: group 0; 2: a high group
+// of 5..8 qubits; 1: a high group of at most 4 qubits)
+hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,
                            PassOps ops, Partials part, int lut_max, hipStream_t s);
-hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
+hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,
                            PassOps ops, Partials part, int lut_max, hipStream_t s);
 hipError_t launch_small(uint8_t* ws, const SubDesc* subs, const int32_t* list, int nlist, int p,
                         int grad, Partials part, int lut_max, hipStream_t s);

@@ -106,100 +106,149 @@ __global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back,
 }
 
 constexpr int SEL_THREADS = 1024;
-constexpr int SEL_MAX = 8192;  // largest beam width
+constexpr int SEL_BINS = 4096;
 
-// Keep the Wsel largest keys among keys[0..N); write them in path order as
-// survivors and their count. One workgroup: radix select on 8-bit digits,
-// compaction, then a bitonic sort on the order word.
+__device__ inline int64_t key_score(uint64_t k) { return (int64_t)(k >> 32) - 1; }
+
+// block-wide exclusive scan of one int per thread (fixed order)
+__device__ inline int32_t block_exscan(int32_t x, int32_t* buf, int32_t* total)
+{
+    const int tid = threadIdx.x;
+    buf[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < SEL_THREADS; off <<= 1) {
+        const int32_t y = tid >= off ? buf[tid - off] : 0;
+        __syncthreads();
+        buf[tid] += y;
+        __syncthreads();
+    }
+    const int32_t incl = buf[tid];
+    *total = buf[SEL_THREADS - 1];
+    __syncthreads();
+    return incl - x;
+}
+
+// Keep the Wsel best keys among keys[0..N) (N = paths * Kmul, key index =
+// path order) by (score desc, index asc) and write them as survivors in
+// index order. One workgroup: (1) best score and number of valid keys;
+// (2) histogram of (hi - score) over a window of 4096 scores to find the
+// threshold score s* at which the count reaches Wsel (the window slides down
+// if needed); (3) compaction in index order keeping every key above s* and
+// the first R keys equal to s*.
 __global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* keys, const int32_t* Nptr, int Kmul,
                                                               int Wsel, int first, Surv* surv, int32_t* nsurv)
 {
-    __shared__ uint32_t hist[256];
-    __shared__ uint64_t sel[SEL_MAX];
-    __shared__ uint64_t s_prefix, s_mask;
-    __shared__ int32_t s_remaining, s_count, s_nnz;
+    __shared__ int32_t hist[SEL_BINS];
+    __shared__ int32_t buf[SEL_THREADS];
+    __shared__ int64_t s_best;
+    __shared__ int32_t s_valid, s_found;
+    __shared__ int64_t s_star;
+    __shared__ int32_t s_R;
     const int tid = threadIdx.x;
     const int64_t N = (int64_t)(*Nptr) * Kmul;
     if (tid == 0) {
-        s_nnz = 0;
-        s_count = 0;
+        s_best = 0;
+        s_valid = 0;
     }
     __syncthreads();
-    int nnz_local = 0;
-    for (int64_t q = tid; q < N; q += SEL_THREADS) nnz_local += keys[q] != 0ull;
-    atomicAdd(&s_nnz, nnz_local);
-    __syncthreads();
-    const int nnz = s_nnz;
-    uint64_t thr = 1ull;  // select every nonzero key when there are at most Wsel
-    if (nnz > Wsel) {
-        if (tid == 0) {
-            s_prefix = 0;
-            s_mask = 0;
-            s_remaining = Wsel;
-        }
-        __syncthreads();
-        for (int pos = 7; pos >= 0; --pos) {
-            for (int b = tid; b < 256; b += SEL_THREADS) hist[b] = 0;
-            __syncthreads();
-            const uint64_t prefix = s_prefix, mask = s_mask;
-            for (int64_t q = tid; q < N; q += SEL_THREADS) {
-                const uint64_t k = keys[q];
-                if (k != 0ull && (k & mask) == prefix) atomicAdd(&hist[(k >> (8 * pos)) & 255u], 1u);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int rem = s_remaining;
-                int b = 255;
-                for (; b >= 0; --b) {
-                    if ((int)hist[b] >= rem) break;
-                    rem -= (int)hist[b];
-                }
-                s_remaining = rem;
-                s_prefix = prefix | ((uint64_t)b << (8 * pos));
-                s_mask = mask | (255ull << (8 * pos));
-            }
-            __syncthreads();
-        }
-        thr = s_prefix;  // the Wsel-th largest key (keys are unique)
-    }
-    const int count = nnz < Wsel ? nnz : Wsel;
+    int64_t best = INT64_MIN;
+    int32_t valid = 0;
     for (int64_t q = tid; q < N; q += SEL_THREADS) {
         const uint64_t k = keys[q];
-        if (k != 0ull && k >= thr) {
-            const int slot = atomicAdd(&s_count, 1);
-            if (slot < SEL_MAX) sel[slot] = k;
+        if (k) {
+            ++valid;
+            const int64_t sc = key_score(k);
+            best = sc > best ? sc : best;
         }
     }
+    atomicAdd(&s_valid, valid);
+    if (valid) atomicMax((unsigned long long*)&s_best, (unsigned long long)best);  // scores are >= 0
     __syncthreads();
-    int n2 = 1;
-    while (n2 < count) n2 <<= 1;
-    for (int q = count + tid; q < n2; q += SEL_THREADS) sel[q] = 0ull;
-    __syncthreads();
-    // sort by the order word: larger low word = earlier path order
-    for (int size = 2; size <= n2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int q = tid; q < (n2 >> 1); q += SEL_THREADS) {
-                const int lo = 2 * stride * (q / stride) + (q % stride);
-                const int hi = lo + stride;
-                const uint64_t a = sel[lo], b = sel[hi];
-                const uint32_t la = (uint32_t)a, lb = (uint32_t)b;
-                const bool desc = (lo & size) == 0;
-                if (desc ? (la < lb) : (la > lb)) {
-                    sel[lo] = b;
-                    sel[hi] = a;
-                }
+    const int32_t nvalid = s_valid;
+    const int64_t hi0 = s_best;
+    const int count = nvalid < Wsel ? nvalid : Wsel;
+    if (nvalid <= Wsel) {
+        if (tid == 0) {
+            s_star = INT64_MIN;  // every valid key is above the threshold
+            s_R = 0;
+        }
+    } else {
+        int64_t hi = hi0;
+        int32_t above = 0;  // keys with score > hi
+        for (;;) {
+            for (int b = tid; b < SEL_BINS; b += SEL_THREADS) hist[b] = 0;
+            if (tid == 0) s_found = 0;
+            __syncthreads();
+            for (int64_t q = tid; q < N; q += SEL_THREADS) {
+                const uint64_t k = keys[q];
+                if (!k) continue;
+                const int64_t d = hi - key_score(k);
+                if (d >= 0 && d < SEL_BINS) atomicAdd(&hist[d], 1);
             }
+            __syncthreads();
+            // each thread owns 4 consecutive bins
+            int32_t h4[4], part = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                h4[i] = hist[4 * tid + i];
+                part += h4[i];
+            }
+            int32_t win_total;
+            const int32_t before = above + block_exscan(part, buf, &win_total);
+            int32_t run = before;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (run < Wsel && run + h4[i] >= Wsel) {
+                    s_star = hi - (4 * tid + i);
+                    s_R = Wsel - run;
+                    s_found = 1;
+                }
+                run += h4[i];
+            }
+            __syncthreads();
+            if (s_found) break;
+            above += win_total;
+            hi -= SEL_BINS;
             __syncthreads();
         }
     }
-    for (int r = tid; r < count; r += SEL_THREADS) {
-        const uint64_t k = sel[r];
-        const uint32_t order = 0xFFFFFFFFu - (uint32_t)k;
-        Surv s;
-        s.parent = first ? 0 : (int32_t)(order / (uint32_t)Kmul);
-        s.digit = first ? (int32_t)order : (int32_t)(order % (uint32_t)Kmul);
-        s.score = (int64_t)(k >> 32) - 1;
-        surv[r] = s;
+    __syncthreads();
+    const int64_t star = s_star;
+    const int32_t R = s_R;
+    // compaction in index order: thread t owns the chunk [t*C, (t+1)*C)
+    const int64_t C = (N + SEL_THREADS - 1) / SEL_THREADS;
+    const int64_t lo = (int64_t)tid * C, up = lo + C < N ? lo + C : N;
+    int32_t gt = 0, eq = 0;
+    for (int64_t q = lo; q < up; ++q) {
+        const uint64_t k = keys[q];
+        if (!k) continue;
+        const int64_t sc = key_score(k);
+        gt += sc > star;
+        eq += sc == star;
+    }
+    int32_t tot;
+    int32_t gt_before = block_exscan(gt, buf, &tot);
+    int32_t eq_before = block_exscan(eq, buf, &tot);
+    for (int64_t q = lo; q < up; ++q) {
+        const uint64_t k = keys[q];
+        if (!k) continue;
+        const int64_t sc = key_score(k);
+        bool take = false;
+        if (sc > star) {
+            take = true;
+        } else if (sc == star) {
+            take = eq_before < R;
+        }
+        if (take) {
+            const int pos = gt_before + (eq_before < R ? eq_before : R);
+            Surv sv;
+            sv.parent = first ? 0 : (int32_t)(q / Kmul);
+            sv.digit = first ? (int32_t)q : (int32_t)(q % Kmul);
+            sv.score = sc;
+            surv[pos] = sv;
+        }
+        if (sc > star) ++gt_before;
+        else if (sc == star) ++eq_before;
     }
     if (tid == 0) *nsurv = count;
 }

@@ -12,7 +12,7 @@
 // group 0 = qubits 0..11 (a tile is 4096 contiguous amplitudes), groups 1..
 // = up to 8 higher qubits each (a tile is 2^(12-nb) contiguous amplitudes
 // times 2^nb strided rows). A workgroup keeps its tile in registers (16
-// amplitudes per lane) and applies the RX rotations of 4 register-resident
+// amplitudes per lane) and applies the rotations of 4 register-resident
 // qubits at a time; between rounds the tile changes register layout through
 // LDS. Consecutive layers visit the groups in alternating (serpentine) order,
 // so the last group of layer l and the first group of layer l+1 share one
@@ -21,7 +21,23 @@
 // table e^{-i gamma c} rounded to complex64. <C> and the gradient inner
 // products are accumulated in FP64 per tile and reduced per subgraph in a
 // fixed order, so every result is bit-reproducible.
+//
+// Rotation arithmetic: e^{-i beta X} = c (I - i t X) with t = tan beta when
+// |cos| >= |sin|, else -i s (X + i k I) with k = cot beta. The bracketed
+// operator costs two FMAs per real component; the per-qubit factor (c or
+// -i s) of a whole group is applied once per segment, folded into the next
+// phase multiply when there is one. Gradient inner products taken on scaled
+// states are rescaled by the known |factor|^2 powers.
 #include "common.h"
+
+// Occupancy targets of the tile passes (waves per SIMD): the register budget
+// the compiler may use is 512 / target VGPRs per lane.
+#ifndef PQ_FWD_WAVES
+#define PQ_FWD_WAVES 4
+#endif
+#ifndef PQ_BWD_WAVES
+#define PQ_BWD_WAVES 2
+#endif
 
 namespace pq {
 
@@ -35,25 +51,6 @@ struct Geo {
     int nb;       // qubits in the group (active tile bits = [c, 12))
 };
 
-__device__ inline Geo group_geo(const SubDesc& d, int g, uint32_t t)
-{
-    Geo r;
-    if (g == 0) {
-        r.c = 0;
-        r.g0 = 0;
-        r.nb = TILE_BITS;
-        r.zb = t << TILE_BITS;
-    } else {
-        r.nb = d.gsize[g];
-        r.g0 = d.gstart[g];
-        r.c = TILE_BITS - r.nb;
-        const int L = r.g0 - r.c;  // fixed bits between the passive block and the group
-        const uint32_t tlo = t & ((1u << L) - 1u), thi = t >> L;
-        r.zb = (tlo << r.c) | (thi << (r.g0 + r.nb));
-    }
-    return r;
-}
-
 // tile position q -> z offset (bit deposit; zb supplies the fixed bits)
 __device__ inline uint32_t gmap(const Geo& g, uint32_t q)
 {
@@ -66,166 +63,123 @@ __device__ inline uint32_t gmap(const Geo& g, uint32_t q)
 // LL1 : lanes = bits 0..3 and 8..11, registers = bits 4..7
 enum { LLIN = 0, LL0 = 1, LL1 = 2 };
 
-__device__ inline uint32_t thread_part(int L, uint32_t tid)
+template <int L>
+__device__ inline uint32_t thread_part(uint32_t tid)
 {
     return L == LLIN ? tid : (L == LL0 ? (tid << 4) : ((tid & 15u) | ((tid >> 4) << 8)));
 }
-__device__ inline uint32_t reg_part(int L, uint32_t r)
+template <int L>
+__host__ __device__ constexpr uint32_t reg_part(uint32_t r)
 {
     return L == LLIN ? (r << 8) : (L == LL0 ? r : (r << 4));
 }
-__device__ inline int layout_bit0(int L) { return L == LLIN ? 8 : (L == LL0 ? 0 : 4); }
-__device__ inline uint32_t lds_idx(uint32_t q) { return q + (q >> 4); }
+template <int L>
+__host__ __device__ constexpr int layout_bit0()
+{
+    return L == LLIN ? 8 : (L == LL0 ? 0 : 4);
+}
+// padded LDS slot; lds_idx(a | b) = lds_idx(a) + lds_idx(b) for disjoint bits
+__host__ __device__ constexpr uint32_t lds_idx(uint32_t q) { return q + (q >> 4); }
 
 // register bits whose tile bit is an active qubit of the group
-__device__ inline unsigned active_mask(int L, int c)
+template <int L>
+__device__ inline unsigned active_mask(int c)
 {
     unsigned m = 0;
-    const int b0 = layout_bit0(L);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-        if (b0 + k >= c) m |= 1u << k;
+        if (layout_bit0<L>() + k >= c) m |= 1u << k;
     return m;
 }
 
-struct Chain {
-    int len;
-    int l[3];
+// Layout chains per group shape: CH = 3 (group 0: every tile bit active),
+// 2 (a high group of 5..8 qubits), 1 (a high group of at most 4 qubits).
+template <int CH, int I>
+struct ChainAt {
+    static constexpr int L = (CH == 3) ? (I == 0 ? LLIN : (I == 1 ? LL0 : LL1)) : (CH == 2 ? (I == 0 ? LLIN : LL1) : LLIN);
 };
 
-// layouts visited to bring every active tile bit into registers once
-__device__ inline Chain group_chain(int g, int nb)
+template <int L>
+__device__ inline void lds_write(float2* lds, uint32_t tid, const float2 (&v)[REGS])
 {
-    Chain c;
-    if (g == 0) {
-        c.len = 3;
-        c.l[0] = LLIN;
-        c.l[1] = LL0;
-        c.l[2] = LL1;
-    } else if (nb >= 5) {
-        c.len = 2;
-        c.l[0] = LLIN;
-        c.l[1] = LL1;
-        c.l[2] = LL1;
-    } else {
-        c.len = 1;
-        c.l[0] = c.l[1] = c.l[2] = LLIN;
-    }
-    return c;
-}
-
-__device__ inline void lds_write(float2* lds, int L, uint32_t tid, const float2 (&v)[REGS])
-{
-    const uint32_t tp = thread_part(L, tid);
+    float2* p = lds + lds_idx(thread_part<L>(tid));
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) lds[lds_idx(tp | reg_part(L, r))] = v[r];
+    for (int r = 0; r < REGS; ++r) p[lds_idx(reg_part<L>(r))] = v[r];
 }
 
-__device__ inline void lds_read(const float2* lds, int L, uint32_t tid, float2 (&v)[REGS])
+template <int L>
+__device__ inline void lds_read(const float2* lds, uint32_t tid, float2 (&v)[REGS])
 {
-    const uint32_t tp = thread_part(L, tid);
+    const float2* p = lds + lds_idx(thread_part<L>(tid));
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) v[r] = lds[lds_idx(tp | reg_part(L, r))];
+    for (int r = 0; r < REGS; ++r) v[r] = p[lds_idx(reg_part<L>(r))];
 }
 
-__device__ inline void xchg(float2* lds, int from, int to, uint32_t tid, float2 (&v)[REGS])
+template <int LF, int LT>
+__device__ inline void xchg(float2* lds, uint32_t tid, float2 (&v)[REGS])
 {
-    lds_write(lds, from, tid, v);
+    lds_write<LF>(lds, tid, v);
     __syncthreads();
-    lds_read(lds, to, tid, v);
+    lds_read<LT>(lds, tid, v);
     __syncthreads();
 }
 
-// (a, b) <- (c a - i s b, -i s a + c b): e^{-i beta X} on one amplitude pair
-// with c = cos beta, s = sin beta (s -> -s gives the inverse).
-__device__ inline void rx_pair(float2& a, float2& b, float c, float s)
+// Reduced pair rotations (see the header comment): mode 0 is
+// (a, b) -> (a - i t b, b - i t a); mode 1 is (a, b) -> (b + i t a, a + i t b).
+// The inverse rotation is the same operator with -t.
+__device__ inline void rx_tan(float2& a, float2& b, float t)
 {
-    const float2 na = make_float2(c * a.x + s * b.y, c * a.y - s * b.x);
-    const float2 nb = make_float2(c * b.x + s * a.y, c * b.y - s * a.x);
+    const float2 na = make_float2(a.x + t * b.y, a.y - t * b.x);
+    const float2 nb = make_float2(b.x + t * a.y, b.y - t * a.x);
+    a = na;
+    b = nb;
+}
+__device__ inline void rx_cot(float2& a, float2& b, float t)
+{
+    const float2 na = make_float2(b.x - t * a.y, b.y + t * a.x);
+    const float2 nb = make_float2(a.x - t * b.y, a.y + t * b.x);
     a = na;
     b = nb;
 }
 
-__device__ inline void rx_regs(float2 (&v)[REGS], unsigned mask, float c, float s)
+template <int MODE>
+__device__ inline void rx_bit(float2 (&v)[REGS], int k, float t)
 {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (mask & (1u << k)) {
-#pragma unroll
-            for (int r = 0; r < REGS; ++r)
-                if (!(r & (1 << k))) rx_pair(v[r], v[r | (1 << k)], c, s);
-        }
+    for (int r = 0; r < REGS; ++r) {
+        if (r & (1 << k)) continue;
+        if (MODE == 0) rx_tan(v[r], v[r | (1 << k)], t);
+        else rx_cot(v[r], v[r | (1 << k)], t);
     }
 }
 
-// sum over active register bits of Im conj(lam(z)) psi(z ^ bit), both ways
-__device__ inline float xb_regs(const float2 (&ps)[REGS], const float2 (&la)[REGS], unsigned mask)
+__device__ inline void rx_regs(float2 (&v)[REGS], unsigned mask, int mode, float t)
+{
+    if (mode == 0) {
+        if (mask & 1u) rx_bit<0>(v, 0, t);
+        if (mask & 2u) rx_bit<0>(v, 1, t);
+        if (mask & 4u) rx_bit<0>(v, 2, t);
+        if (mask & 8u) rx_bit<0>(v, 3, t);
+    } else {
+        if (mask & 1u) rx_bit<1>(v, 0, t);
+        if (mask & 2u) rx_bit<1>(v, 1, t);
+        if (mask & 4u) rx_bit<1>(v, 2, t);
+        if (mask & 8u) rx_bit<1>(v, 3, t);
+    }
+}
+
+// sum over one register bit of Im conj(lam(z)) psi(z ^ bit), both directions
+__device__ inline float xb_bit(const float2 (&ps)[REGS], const float2 (&la)[REGS], int k)
 {
     float acc = 0.f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (mask & (1u << k)) {
-#pragma unroll
-            for (int r = 0; r < REGS; ++r) {
-                if (r & (1 << k)) continue;
-                const int r1 = r | (1 << k);
-                acc += la[r].x * ps[r1].y - la[r].y * ps[r1].x;
-                acc += la[r1].x * ps[r].y - la[r1].y * ps[r].x;
-            }
-        }
+    for (int r = 0; r < REGS; ++r) {
+        if (r & (1 << k)) continue;
+        const int r1 = r | (1 << k);
+        acc += la[r].x * ps[r1].y - la[r].y * ps[r1].x;
+        acc += la[r1].x * ps[r].y - la[r1].y * ps[r].x;
     }
     return acc;
-}
-
-__device__ inline int cur_layout(const Chain& ch, bool at_start) { return at_start ? ch.l[0] : ch.l[ch.len - 1]; }
-
-// RX of one layer on every qubit of the group, walking the layout chain from
-// the current end to the other one.
-__device__ inline void seg_fwd(float2 (&v)[REGS], float2* lds, const Chain& ch, bool& at_start, int c,
-                               float cs, float sn, uint32_t tid)
-{
-    if (at_start) {
-        for (int i = 0; i < ch.len; ++i) {
-            if (i > 0) xchg(lds, ch.l[i - 1], ch.l[i], tid, v);
-            rx_regs(v, active_mask(ch.l[i], c), cs, sn);
-        }
-    } else {
-        for (int i = ch.len - 1; i >= 0; --i) {
-            if (i < ch.len - 1) xchg(lds, ch.l[i + 1], ch.l[i], tid, v);
-            rx_regs(v, active_mask(ch.l[i], c), cs, sn);
-        }
-    }
-    at_start = !at_start;
-}
-
-// inverse RX on psi and lambda, accumulating the beta-gradient inner product
-__device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* lds, const Chain& ch,
-                               bool& at_start, int c, float cs, float sn, uint32_t tid, double& xacc)
-{
-    if (at_start) {
-        for (int i = 0; i < ch.len; ++i) {
-            if (i > 0) {
-                xchg(lds, ch.l[i - 1], ch.l[i], tid, ps);
-                xchg(lds, ch.l[i - 1], ch.l[i], tid, la);
-            }
-            const unsigned m = active_mask(ch.l[i], c);
-            xacc += (double)xb_regs(ps, la, m);
-            rx_regs(ps, m, cs, -sn);
-            rx_regs(la, m, cs, -sn);
-        }
-    } else {
-        for (int i = ch.len - 1; i >= 0; --i) {
-            if (i < ch.len - 1) {
-                xchg(lds, ch.l[i + 1], ch.l[i], tid, ps);
-                xchg(lds, ch.l[i + 1], ch.l[i], tid, la);
-            }
-            const unsigned m = active_mask(ch.l[i], c);
-            xacc += (double)xb_regs(ps, la, m);
-            rx_regs(ps, m, cs, -sn);
-            rx_regs(la, m, cs, -sn);
-        }
-    }
-    at_start = !at_start;
 }
 
 __device__ inline float2 cmul(float2 a, float2 b)
@@ -233,16 +187,117 @@ __device__ inline float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// C(z) for the 16 amplitudes a lane holds in layout L. Group 0 reads the
-// natural-order table, the last group its tile-order copy.
-__device__ inline void load_cut(uint16_t (&cr)[REGS], const uint8_t* ws, const SubDesc& d, int g,
-                                const Geo& geo, uint32_t t, int L, uint32_t tid)
+__device__ inline void scale_regs(float2 (&v)[REGS], float2 f)
 {
-    const uint32_t tp = thread_part(L, tid);
-    const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + d.tab) + geo.zb
-                                   : (const uint16_t*)(ws + d.tabB) + (size_t)t * TILE;
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) cr[r] = tab[tp | reg_part(L, r)];
+    for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], f);
+}
+
+// Per-layer rotation parameters (built in FP64 by the angle-prep kernel).
+struct RxC {
+    float t;
+    int mode;
+    float fsq;  // |per-qubit factor|^2
+    float2 Ff, Fi;  // whole-group factors of this pass's group (forward, inverse)
+};
+
+__device__ inline RxC load_rx(const RxCoef* cf, int l, int g)
+{
+    RxC r;
+    r.t = cf[l].t;
+    r.mode = cf[l].mode;
+    r.fsq = cf[l].fsq;
+    r.Ff = cf[l].Ff[g];
+    r.Fi = cf[l].Fi[g];
+    return r;
+}
+
+// One RX segment (all qubits of the group, one layer) walking the layout
+// chain in direction DIR (true: start -> end). Forward rotation, no factor.
+template <int CH, bool DIR>
+__device__ inline void seg_fwd(float2 (&v)[REGS], float2* lds, int c, int mode, float t, uint32_t tid)
+{
+    constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
+    rx_regs(v, active_mask<L0>(c), mode, t);
+    if constexpr (CH >= 2) {
+        constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
+        xchg<L0, L1>(lds, tid, v);
+        rx_regs(v, active_mask<L1>(c), mode, t);
+        if constexpr (CH >= 3) {
+            constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
+            xchg<L1, L2>(lds, tid, v);
+            rx_regs(v, active_mask<L2>(c), mode, t);
+        }
+    }
+}
+
+// Inverse rotation on psi and lambda with the beta-gradient terms. A round's
+// inner products are all taken before its rotations, on states scaled by
+// |f|^(-done) (done = qubits already rotated in earlier rounds of this
+// segment), so they are multiplied back by fsq^done.
+template <int L>
+__device__ inline void bwd_round(float2 (&ps)[REGS], float2 (&la)[REGS], int c, int mode, float t, float fsq,
+                                 float& wdone, double& xacc)
+{
+    const unsigned m = active_mask<L>(c);
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (m & (1u << k)) a += xb_bit(ps, la, k);
+    // every bit of this round sees the same scale (no rotation yet this round)
+    xacc += (double)(wdone * a);
+    rx_regs(ps, m, mode, -t);
+    rx_regs(la, m, mode, -t);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (m & (1u << k)) wdone *= fsq;
+}
+
+template <int CH, bool DIR>
+__device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* lds, int c, const RxC& rc,
+                               uint32_t tid, double& xacc)
+{
+    float wdone = 1.f;
+    constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
+    bwd_round<L0>(ps, la, c, rc.mode, rc.t, rc.fsq, wdone, xacc);
+    if constexpr (CH >= 2) {
+        constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
+        xchg<L0, L1>(lds, tid, ps);
+        xchg<L0, L1>(lds, tid, la);
+        bwd_round<L1>(ps, la, c, rc.mode, rc.t, rc.fsq, wdone, xacc);
+        if constexpr (CH >= 3) {
+            constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
+            xchg<L1, L2>(lds, tid, ps);
+            xchg<L1, L2>(lds, tid, la);
+            bwd_round<L2>(ps, la, c, rc.mode, rc.t, rc.fsq, wdone, xacc);
+        }
+    }
+}
+
+// C(z) for the 16 amplitudes a lane holds in layout L (group 0: natural
+// table; the last group: its tile-order copy, contiguous per tile).
+template <int L>
+__device__ inline void load_cut_L(uint16_t (&cr)[REGS], const uint16_t* tab, uint32_t tid)
+{
+    const uint16_t* p = tab + thread_part<L>(tid);
+#pragma unroll
+    for (int r = 0; r < REGS; ++r) cr[r] = p[reg_part<L>(r)];
+}
+
+template <int L>
+__device__ inline void load_state(float2 (&v)[REGS], const float2* st, const Geo& geo, uint32_t tid)
+{
+    const float2* p = st + (geo.zb | gmap(geo, thread_part<L>(tid)));
+#pragma unroll
+    for (int r = 0; r < REGS; ++r) v[r] = p[gmap(geo, reg_part<L>(r))];
+}
+
+template <int L>
+__device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Geo& geo, uint32_t tid)
+{
+    float2* p = st + (geo.zb | gmap(geo, thread_part<L>(tid)));
+#pragma unroll
+    for (int r = 0; r < REGS; ++r) p[gmap(geo, reg_part<L>(r))] = v[r];
 }
 
 // deterministic block sum (wave64 butterfly, then the 4 wave totals in order)
@@ -270,107 +325,165 @@ __device__ inline uint32_t cut_of(uint32_t z, const int32_t* E, int ne)
     return c;
 }
 
+__device__ inline Geo make_geo(const SubDesc* sd, int g, uint32_t t)
+{
+    Geo r;
+    if (g == 0) {
+        r.c = 0;
+        r.g0 = 0;
+        r.nb = TILE_BITS;
+        r.zb = t << TILE_BITS;
+    } else {
+        r.nb = sd->gsize[g];
+        r.g0 = sd->gstart[g];
+        r.c = TILE_BITS - r.nb;
+        const int L = r.g0 - r.c;  // fixed bits between the passive block and the group
+        const uint32_t tlo = t & ((1u << L) - 1u), thi = t >> L;
+        r.zb = (tlo << r.c) | (thi << (r.g0 + r.nb));
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // K1: integer cut tables (natural order + tile order of the last group)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(THREADS) void k_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work)
 {
     const int2 wk = work[blockIdx.x];
-    const SubDesc d = subs[wk.x];
+    const SubDesc* sd = subs + wk.x;
     const uint32_t t = (uint32_t)wk.y;
-    const int32_t* E = (const int32_t*)(ws + d.edges);
-    uint16_t* tab = (uint16_t*)(ws + d.tab);
-    const uint32_t dim = 1u << d.n;
+    const int n = sd->n, ne = sd->nedges, G = sd->ngroups;
+    const int32_t* E = (const int32_t*)(ws + sd->edges);
+    uint16_t* tab = (uint16_t*)(ws + sd->tab);
+    const uint32_t dim = 1u << n;
     const uint32_t span = dim < (uint32_t)TILE ? dim : (uint32_t)TILE;
+    const Geo geo = make_geo(sd, G >= 2 ? G - 1 : 0, t);
+    uint16_t* tabB = (uint16_t*)(ws + sd->tabB);
     for (uint32_t q = threadIdx.x; q < span; q += THREADS) {
         const uint32_t z = t * TILE + q;
-        tab[z] = (uint16_t)cut_of(z, E, d.nedges);
-        if (d.ngroups >= 2) {
-            const Geo geo = group_geo(d, d.ngroups - 1, t);
-            uint16_t* tabB = (uint16_t*)(ws + d.tabB);
-            tabB[(size_t)t * TILE + q] = (uint16_t)cut_of(geo.zb | gmap(geo, q), E, d.nedges);
-        }
+        tab[z] = (uint16_t)cut_of(z, E, ne);
+        if (G >= 2) tabB[(size_t)t * TILE + q] = (uint16_t)cut_of(geo.zb | gmap(geo, q), E, ne);
     }
 }
 
 // ---------------------------------------------------------------------------
 // K2: angle preparation. LUT[c] = e^{-i gamma c} from an FP64 product and
-// FP64 sine/cosine, rounded to complex64; (cos beta, sin beta) as float.
+// FP64 sine/cosine, rounded to complex64; the rotation parameters of the
+// layer in FP64, rounded to float.
 // ---------------------------------------------------------------------------
+__device__ inline void cpow_d(double re, double im, int e, double& ore, double& oim)
+{
+    double r = 1.0, i = 0.0;
+    for (int k = 0; k < e; ++k) {
+        const double nr = r * re - i * im, ni = r * im + i * re;
+        r = nr;
+        i = ni;
+    }
+    ore = r;
+    oim = i;
+}
+
 __global__ __launch_bounds__(THREADS) void k_angle_prep(uint8_t* ws, const SubDesc* subs, int p,
                                                         const double* gamma, const double* beta)
 {
     const int b = blockIdx.x / p, l = blockIdx.x % p;
-    const SubDesc d = subs[b];
+    const SubDesc* sd = subs + b;
+    const int lut_len = sd->lut_len;
     const double gm = gamma[(size_t)b * p + l];
-    float2* lut = (float2*)(ws + d.lut) + (size_t)l * d.lut_len;
-    for (int c = threadIdx.x; c < d.lut_len; c += THREADS) {
+    float2* lut = (float2*)(ws + sd->lut) + (size_t)l * lut_len;
+    for (int c = threadIdx.x; c < lut_len; c += THREADS) {
         double sv, cv;
         sincos(gm * (double)c, &sv, &cv);
         lut[c] = make_float2((float)cv, (float)(-sv));
     }
     if (threadIdx.x == 0) {
         const double bt = beta[(size_t)b * p + l];
-        ((float2*)(ws + d.coef))[l] = make_float2((float)cos(bt), (float)sin(bt));
+        double s, c;
+        sincos(bt, &s, &c);
+        RxCoef rc;
+        rc.cs = make_float2((float)c, (float)s);
+        const bool tanm = fabs(c) >= fabs(s);
+        rc.mode = tanm ? 0 : 1;
+        rc.t = (float)(tanm ? s / c : c / s);
+        rc.fsq = (float)(tanm ? c * c : s * s);
+        // per-qubit factors: forward c or -i s, inverse c or +i s
+        const double fr = tanm ? c : 0.0, fi_f = tanm ? 0.0 : -s, fi_i = tanm ? 0.0 : s;
+        for (int g = 0; g < MAX_GROUPS; ++g) {
+            const int nq = g < sd->ngroups ? sd->gsize[g] : 0;
+            double r, i;
+            cpow_d(fr, fi_f, nq, r, i);
+            rc.Ff[g] = make_float2((float)r, (float)i);
+            cpow_d(fr, fi_i, nq, r, i);
+            rc.Fi[g] = make_float2((float)r, (float)i);
+        }
+        ((RxCoef*)(ws + sd->coef))[l] = rc;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Forward tile pass: [init | load] RX(pre) phase(ph) RX(post) [<C> partial] store
+// Forward tile pass: [init | load] RX(pre) phase(ph) RX(post) [<C>] store
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(THREADS) void k_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
+template <int CH>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_WAVES))) void k_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
                                                       PassOps ops, Partials part)
 {
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* lut = smem + LDS_TILE;
     __shared__ double red[THREADS / 64];
+    constexpr int LS = ChainAt<CH, 0>::L, LE = ChainAt<CH, CH - 1>::L;
     const uint32_t tid = threadIdx.x;
     const int2 wk = work[blockIdx.x];
-    const SubDesc d = subs[wk.x];
+    const SubDesc* sd = subs + wk.x;
     const uint32_t t = (uint32_t)wk.y;
     const int g = ops.group;
-    const Geo geo = group_geo(d, g, t);
-    const Chain ch = group_chain(g, geo.nb);
-    float2* st = (float2*)(ws + d.psi);
-    const float2* coef = (const float2*)(ws + d.coef);
+    const Geo geo = make_geo(sd, g, t);
+    float2* st = (float2*)(ws + sd->psi);
+    const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
+    const int lut_len = sd->lut_len;
+    const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + sd->tab) + geo.zb
+                                   : (const uint16_t*)(ws + sd->tabB) + (size_t)t * TILE;
 
+    RxC pre{}, post{};
+    if (ops.pre >= 0) pre = load_rx(cf, ops.pre, g);
+    if (ops.post >= 0) post = load_rx(cf, ops.post, g);
+    // phase table, with the factor of the segment before it folded in
     if (ops.ph >= 0) {
-        const float2* L = (const float2*)(ws + d.lut) + (size_t)ops.ph * d.lut_len;
-        for (int i = tid; i < d.lut_len; i += THREADS) lut[i] = L[i];
+        const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
+        const float2 F = ops.pre >= 0 ? pre.Ff : make_float2(1.f, 0.f);
+        for (int i = tid; i < lut_len; i += THREADS) lut[i] = cmul(L[i], F);
     }
     const int nseg = (ops.pre >= 0) + (ops.post >= 0);
+    const bool cut_at_end = (ops.ph >= 0) ? (ops.pre >= 0) : (nseg & 1);
     uint16_t cr[REGS];
     if (ops.ph >= 0 || ops.epi_e) {
-        // the phase comes after RX(pre); <C> after all segments
-        const bool at_end = (ops.ph >= 0) ? (ops.pre >= 0) : (nseg & 1);
-        load_cut(cr, ws, d, g, geo, t, at_end ? ch.l[ch.len - 1] : ch.l[0], tid);
+        if (cut_at_end) load_cut_L<LE>(cr, tab, tid);
+        else load_cut_L<LS>(cr, tab, tid);
     }
     float2 v[REGS];
-    {
-        const uint32_t base = geo.zb | gmap(geo, thread_part(LLIN, tid));
-        if (ops.init) {
-            const float a = (float)(1.0 / sqrt((double)(1ull << d.n)));
+    if (ops.init) {
+        const float a = (float)(1.0 / sqrt((double)(1ull << sd->n)));
 #pragma unroll
-            for (int r = 0; r < REGS; ++r) v[r] = make_float2(a, 0.f);
-        } else {
-#pragma unroll
-            for (int r = 0; r < REGS; ++r) v[r] = st[base | gmap(geo, reg_part(LLIN, r))];
-        }
+        for (int r = 0; r < REGS; ++r) v[r] = make_float2(a, 0.f);
+    } else {
+        load_state<LS>(v, st, geo, tid);
     }
     __syncthreads();  // phase table staged
     bool at_start = true;
     if (ops.pre >= 0) {
-        const float2 cf = coef[ops.pre];
-        seg_fwd(v, lds, ch, at_start, geo.c, cf.x, cf.y, tid);
+        seg_fwd<CH, true>(v, lds, geo.c, pre.mode, pre.t, tid);
+        at_start = false;
+        if (ops.ph < 0) scale_regs(v, pre.Ff);
     }
     if (ops.ph >= 0) {
 #pragma unroll
         for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
     }
     if (ops.post >= 0) {
-        const float2 cf = coef[ops.post];
-        seg_fwd(v, lds, ch, at_start, geo.c, cf.x, cf.y, tid);
+        if (at_start) seg_fwd<CH, true>(v, lds, geo.c, post.mode, post.t, tid);
+        else seg_fwd<CH, false>(v, lds, geo.c, post.mode, post.t, tid);
+        at_start = !at_start;
+        scale_regs(v, post.Ff);
     }
     if (ops.epi_e) {
         double acc = 0.0;
@@ -378,12 +491,10 @@ __global__ __launch_bounds__(THREADS) void k_fwd_pass(uint8_t* ws, const SubDesc
         for (int r = 0; r < REGS; ++r)
             acc += ((double)v[r].x * v[r].x + (double)v[r].y * v[r].y) * (double)cr[r];
         acc = block_sum(acc, red);
-        if (tid == 0) part.e[d.tile_base + t] = acc;
+        if (tid == 0) part.e[sd->tile_base + t] = acc;
     }
-    const int L = cur_layout(ch, at_start);
-    const uint32_t base = geo.zb | gmap(geo, thread_part(L, tid));
-#pragma unroll
-    for (int r = 0; r < REGS; ++r) st[base | gmap(geo, reg_part(L, r))] = v[r];
+    if (at_start) store_state<LS>(v, st, geo, tid);
+    else store_state<LE>(v, st, geo, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,80 +505,95 @@ __global__ __launch_bounds__(THREADS) void k_fwd_pass(uint8_t* ws, const SubDesc
 // else : unmix(pre) + beta-grad, gamma-grad + unphase(ph), unmix(post) +
 //        beta-grad; store both unless this is the last pass.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(THREADS) void k_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
+template <int CH>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_WAVES))) void k_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
                                                       PassOps ops, Partials part)
 {
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* lut = smem + LDS_TILE;
     __shared__ double red[THREADS / 64];
+    constexpr int LS = ChainAt<CH, 0>::L, LE = ChainAt<CH, CH - 1>::L;
     const uint32_t tid = threadIdx.x;
     const int2 wk = work[blockIdx.x];
-    const SubDesc d = subs[wk.x];
+    const SubDesc* sd = subs + wk.x;
     const uint32_t t = (uint32_t)wk.y;
     const int g = ops.group;
-    const Geo geo = group_geo(d, g, t);
-    const Chain ch = group_chain(g, geo.nb);
-    float2* sp = (float2*)(ws + d.psi);
-    float2* sl = (float2*)(ws + d.lam);
-    const float2* coef = (const float2*)(ws + d.coef);
+    const Geo geo = make_geo(sd, g, t);
+    float2* sp = (float2*)(ws + sd->psi);
+    float2* sl = (float2*)(ws + sd->lam);
+    const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
+    const int lut_len = sd->lut_len;
     const int T = part.total_tiles;
-    const int tile = d.tile_base + (int)t;
+    const int tile = sd->tile_base + (int)t;
+    const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + sd->tab) + geo.zb
+                                   : (const uint16_t*)(ws + sd->tabB) + (size_t)t * TILE;
 
+    RxC pre{}, post{};
+    if (ops.pre >= 0) pre = load_rx(cf, ops.pre, g);
+    if (ops.post >= 0) post = load_rx(cf, ops.post, g);
+    // conjugate phase table with the inverse factor of the preceding segment
     if (ops.ph >= 0 && !ops.last) {
-        const float2* L = (const float2*)(ws + d.lut) + (size_t)ops.ph * d.lut_len;
-        for (int i = tid; i < d.lut_len; i += THREADS) lut[i] = L[i];
-    }
-    uint16_t cr[REGS];
-    if (ops.fused || ops.ph >= 0) load_cut(cr, ws, d, g, geo, t, ch.l[ch.len - 1], tid);
-
-    float2 ps[REGS], la[REGS];
-    {
-        const uint32_t base = geo.zb | gmap(geo, thread_part(LLIN, tid));
-#pragma unroll
-        for (int r = 0; r < REGS; ++r) ps[r] = sp[base | gmap(geo, reg_part(LLIN, r))];
-        if (!ops.fused) {
-#pragma unroll
-            for (int r = 0; r < REGS; ++r) la[r] = sl[base | gmap(geo, reg_part(LLIN, r))];
+        const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
+        const float2 F = pre.Fi;
+        for (int i = tid; i < lut_len; i += THREADS) {
+            const float2 e = L[i];
+            lut[i] = cmul(make_float2(e.x, -e.y), F);
         }
     }
+    uint16_t cr[REGS];
+    if (ops.fused || ops.ph >= 0) load_cut_L<LE>(cr, tab, tid);
+
+    float2 ps[REGS], la[REGS];
+    load_state<LS>(ps, sp, geo, tid);
+    if (!ops.fused) load_state<LS>(la, sl, geo, tid);
     __syncthreads();
     bool at_start = true;
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
     if (ops.fused) {
-        const float2 cf = coef[ops.pre];
-        seg_fwd(ps, lds, ch, at_start, geo.c, cf.x, cf.y, tid);
+        seg_fwd<CH, true>(ps, lds, geo.c, pre.mode, pre.t, tid);
+        scale_regs(ps, pre.Ff);  // psi_p at true scale
 #pragma unroll
         for (int r = 0; r < REGS; ++r) {
             const float c = (float)cr[r];
             acc_e += ((double)ps[r].x * ps[r].x + (double)ps[r].y * ps[r].y) * (double)cr[r];
             la[r] = make_float2(c * ps[r].x, c * ps[r].y);
         }
-        seg_bwd(ps, la, lds, ch, at_start, geo.c, cf.x, cf.y, tid, acc_pre);
+        seg_bwd<CH, false>(ps, la, lds, geo.c, pre, tid, acc_pre);
+        scale_regs(la, pre.Fi);
     } else {
         if (ops.pre >= 0) {
-            const float2 cf = coef[ops.pre];
-            seg_bwd(ps, la, lds, ch, at_start, geo.c, cf.x, cf.y, tid, acc_pre);
+            seg_bwd<CH, true>(ps, la, lds, geo.c, pre, tid, acc_pre);
+            at_start = false;
         }
         if (ops.ph >= 0) {
+            // on the rotated-but-unscaled states; rescale by |F|^2
             float a = 0.f;
 #pragma unroll
             for (int r = 0; r < REGS; ++r)
                 a += (float)cr[r] * (la[r].x * ps[r].y - la[r].y * ps[r].x);
-            acc_ph = (double)a;
+            const float2 F = pre.Fi;
+            acc_ph = (double)a * (double)(F.x * F.x + F.y * F.y);
             if (!ops.last) {
 #pragma unroll
                 for (int r = 0; r < REGS; ++r) {
-                    float2 f = lut[cr[r]];
-                    f.y = -f.y;
+                    const float2 f = lut[cr[r]];
                     ps[r] = cmul(ps[r], f);
                     la[r] = cmul(la[r], f);
                 }
             }
+        } else if (ops.pre >= 0 && !ops.last) {
+            scale_regs(ps, pre.Fi);
+            scale_regs(la, pre.Fi);
         }
         if (ops.post >= 0) {
-            const float2 cf = coef[ops.post];
-            seg_bwd(ps, la, lds, ch, at_start, geo.c, cf.x, cf.y, tid, acc_post);
+            if (at_start) seg_bwd<CH, true>(ps, la, lds, geo.c, post, tid, acc_post);
+            else seg_bwd<CH, false>(ps, la, lds, geo.c, post, tid, acc_post);
+            at_start = !at_start;
+            if (!ops.last) {
+                scale_regs(ps, post.Fi);
+                scale_regs(la, post.Fi);
+            }
         }
     }
     // partial sums (every thread takes part in each block_sum)
@@ -493,51 +619,64 @@ __global__ __launch_bounds__(THREADS) void k_bwd_pass(uint8_t* ws, const SubDesc
         }
     }
     if (ops.last) return;
-    const int L = cur_layout(ch, at_start);
-    const uint32_t base = geo.zb | gmap(geo, thread_part(L, tid));
-    if (!ops.fused) {
-#pragma unroll
-        for (int r = 0; r < REGS; ++r) sp[base | gmap(geo, reg_part(L, r))] = ps[r];
+    if (ops.fused) {
+        store_state<LS>(la, sl, geo, tid);
+        return;
     }
-#pragma unroll
-    for (int r = 0; r < REGS; ++r) sl[base | gmap(geo, reg_part(L, r))] = la[r];
+    if (at_start) {
+        store_state<LS>(ps, sp, geo, tid);
+        store_state<LS>(la, sl, geo, tid);
+    } else {
+        store_state<LE>(ps, sp, geo, tid);
+        store_state<LE>(la, sl, geo, tid);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Subgraphs with n <= 12: one workgroup runs the whole circuit (and, with
-// grad, the whole adjoint sweep) in LDS, one qubit at a time.
+// grad, the whole adjoint sweep) in LDS, one qubit at a time, with the
+// plain (cos, sin) form of each rotation.
 // ---------------------------------------------------------------------------
+__device__ inline void rx_pair(float2& a, float2& b, float c, float s)
+{
+    const float2 na = make_float2(c * a.x + s * b.y, c * a.y - s * b.x);
+    const float2 nb = make_float2(c * b.x + s * a.y, c * b.y - s * a.x);
+    a = na;
+    b = nb;
+}
+
 __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* subs, const int32_t* list,
                                                    int p, int grad, Partials part)
 {
     extern __shared__ float2 smem[];
     __shared__ double red[THREADS / 64];
     const uint32_t tid = threadIdx.x;
-    const SubDesc d = subs[list[blockIdx.x]];
-    const int n = d.n;
+    const SubDesc* sd = subs + list[blockIdx.x];
+    const int n = sd->n;
     const uint32_t dim = 1u << n, half = dim >> 1;
     float2* ps = smem;
     float2* la = smem + TILE;
     float2* lut = smem + (grad ? 2 * TILE : TILE);
-    const uint16_t* tab = (const uint16_t*)(ws + d.tab);
-    const float2* coef = (const float2*)(ws + d.coef);
-    const float2* luts = (const float2*)(ws + d.lut);
+    const uint16_t* tab = (const uint16_t*)(ws + sd->tab);
+    const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
+    const float2* luts = (const float2*)(ws + sd->lut);
+    const int lut_len = sd->lut_len;
     const int T = part.total_tiles;
-    const int tile = d.tile_base;
+    const int tile = sd->tile_base;
 
     const float a0 = (float)(1.0 / sqrt((double)dim));
     for (uint32_t z = tid; z < dim; z += THREADS) ps[z] = make_float2(a0, 0.f);
     for (int l = 0; l < p; ++l) {
         __syncthreads();
-        for (int i = tid; i < d.lut_len; i += THREADS) lut[i] = luts[(size_t)l * d.lut_len + i];
+        for (int i = tid; i < lut_len; i += THREADS) lut[i] = luts[(size_t)l * lut_len + i];
         __syncthreads();
         for (uint32_t z = tid; z < dim; z += THREADS) ps[z] = cmul(ps[z], lut[tab[z]]);
-        const float2 cf = coef[l];
+        const float2 cs = cf[l].cs;
         for (int j = 0; j < n; ++j) {
             __syncthreads();
             for (uint32_t i = tid; i < half; i += THREADS) {
                 const uint32_t z = ((i >> j) << (j + 1)) | (i & ((1u << j) - 1u));
-                rx_pair(ps[z], ps[z | (1u << j)], cf.x, cf.y);
+                rx_pair(ps[z], ps[z | (1u << j)], cs.x, cs.y);
             }
         }
     }
@@ -548,7 +687,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
     acc = block_sum(acc, red);
     if (tid == 0) part.e[tile] = acc;
     if (!grad) {
-        float2* st = (float2*)(ws + d.psi);
+        float2* st = (float2*)(ws + sd->psi);
         for (uint32_t z = tid; z < dim; z += THREADS) st[z] = ps[z];
         return;
     }
@@ -557,7 +696,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
         la[z] = make_float2(c * ps[z].x, c * ps[z].y);
     }
     for (int l = p - 1; l >= 0; --l) {
-        const float2 cf = coef[l];
+        const float2 cs = cf[l].cs;
         double xb = 0.0;
         for (int j = 0; j < n; ++j) {
             __syncthreads();
@@ -567,8 +706,8 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
                 const uint32_t z1 = z | (1u << j);
                 a += la[z].x * ps[z1].y - la[z].y * ps[z1].x;
                 a += la[z1].x * ps[z].y - la[z1].y * ps[z].x;
-                rx_pair(ps[z], ps[z1], cf.x, -cf.y);
-                rx_pair(la[z], la[z1], cf.x, -cf.y);
+                rx_pair(ps[z], ps[z1], cs.x, -cs.y);
+                rx_pair(la[z], la[z1], cs.x, -cs.y);
             }
             xb += (double)a;
         }
@@ -581,7 +720,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
         gg = block_sum(gg, red);
         if (tid == 0) part.gg[(size_t)l * T + tile] = gg;
         if (l > 0) {
-            for (int i = tid; i < d.lut_len; i += THREADS) lut[i] = luts[(size_t)l * d.lut_len + i];
+            for (int i = tid; i < lut_len; i += THREADS) lut[i] = luts[(size_t)l * lut_len + i];
             __syncthreads();
             for (uint32_t z = tid; z < dim; z += THREADS) {
                 float2 f = lut[tab[z]];
@@ -602,8 +741,8 @@ __global__ __launch_bounds__(THREADS) void k_reduce(const SubDesc* subs, int p, 
 {
     __shared__ double red[THREADS / 64];
     const int b = blockIdx.x;
-    const SubDesc d = subs[b];
-    const int T = part.total_tiles, tb = d.tile_base, nt = d.ntiles;
+    const SubDesc* sd = subs + b;
+    const int T = part.total_tiles, tb = sd->tile_base, nt = sd->ntiles, G = sd->ngroups;
     double acc = 0.0;
     for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.e[tb + i];
     acc = block_sum(acc, red);
@@ -611,7 +750,7 @@ __global__ __launch_bounds__(THREADS) void k_reduce(const SubDesc* subs, int p, 
     if (!grad) return;
     for (int l = 0; l < p; ++l) {
         double xb = 0.0;
-        for (int g = 0; g < d.ngroups; ++g)
+        for (int g = 0; g < G; ++g)
             for (int i = threadIdx.x; i < nt; i += THREADS)
                 xb += part.gb[((size_t)l * MAX_GROUPS + g) * T + tb + i];
         xb = block_sum(xb, red);
@@ -644,21 +783,25 @@ hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, con
 
 static size_t pass_lds(int lut_max) { return (size_t)(LDS_TILE + lut_max) * sizeof(float2); }
 
-hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, PassOps ops,
+hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain, PassOps ops,
                            Partials part, int lut_max, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd_pass, dim3(nwork), dim3(THREADS), pass_lds(lut_max), s, ws, subs, work, ops,
-                       part);
+    const size_t lds = pass_lds(lut_max);
+    if (chain == 3) hipLaunchKernelGGL(k_fwd_pass<3>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
+    else if (chain == 2) hipLaunchKernelGGL(k_fwd_pass<2>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
+    else hipLaunchKernelGGL(k_fwd_pass<1>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
     return hipGetLastError();
 }
 
-hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, PassOps ops,
+hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain, PassOps ops,
                            Partials part, int lut_max, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bwd_pass, dim3(nwork), dim3(THREADS), pass_lds(lut_max), s, ws, subs, work, ops,
-                       part);
+    const size_t lds = pass_lds(lut_max);
+    if (chain == 3) hipLaunchKernelGGL(k_bwd_pass<3>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
+    else if (chain == 2) hipLaunchKernelGGL(k_bwd_pass<2>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
+    else hipLaunchKernelGGL(k_bwd_pass<1>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
     return hipGetLastError();
 }
 

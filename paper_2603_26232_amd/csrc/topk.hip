@@ -70,12 +70,23 @@ __global__ __launch_bounds__(THREADS) void k_topk_tile(const uint8_t* ws, const 
 }
 
 // stage 2: fold the ntiles*k keys of a subgraph into its best k; write results
-__global__ __launch_bounds__(THREADS) void k_topk_merge(const SubDesc* subs, int k, const uint64_t* in,
+__global__ __launch_bounds__(THREADS) void k_topk_merge(const SubDesc* subs, int k, int canonical, const uint64_t* in,
                                                        uint32_t* idx, float* prob)
 {
     __shared__ uint64_t s[SORT_N];
     const int b = blockIdx.x;
     const SubDesc d = subs[b];
+    if (d.skip) {
+        // edgeless subgraph: |psi|^2 = 2^-n everywhere, ties broken by index
+        const uint32_t step = canonical ? 2u : 1u;
+        const uint64_t cnt = (1ull << d.n) / step;
+        for (int i = threadIdx.x; i < k; i += THREADS) {
+            const bool ok = (uint64_t)i < cnt;
+            idx[(size_t)b * k + i] = ok ? (uint32_t)i * step : 0xFFFFFFFFu;
+            prob[(size_t)b * k + i] = ok ? ldexpf(1.0f, -d.n) : -1.0f;
+        }
+        return;
+    }
     const size_t total = (size_t)d.ntiles * k;
     const uint64_t* src = in + (size_t)d.tile_base * k;
     const int chunk = SORT_N / 2;
@@ -107,10 +118,12 @@ hipError_t launch_topk(uint8_t* ws, const SubDesc* subs, const int2* work, int n
                        hipStream_t s)
 {
     (void)keys_b;
-    hipLaunchKernelGGL(k_topk_tile, dim3(nwork), dim3(THREADS), 0, s, ws, subs, work, k, canonical, keys_a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_topk_merge, dim3(B), dim3(THREADS), 0, s, subs, k, keys_a, idx, prob);
+    if (nwork > 0) {
+        hipLaunchKernelGGL(k_topk_tile, dim3(nwork), dim3(THREADS), 0, s, ws, subs, work, k, canonical, keys_a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_topk_merge, dim3(B), dim3(THREADS), 0, s, subs, k, canonical, keys_a, idx, prob);
     return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ class Solver:
     """Holds the device buffers of one graph so repeated solves allocate
     nothing new (the bench times `run`)."""
 
-    def __init__(self, graph, part: Partition, cfg: SolveConfig, device="cuda"):
+    def __init__(self, graph, part: Partition, cfg: SolveConfig, device="cuda", skip_edgeless=False):
         self.g = graph
         self.part = part
         self.cfg = cfg
@@ -60,7 +60,8 @@ class Solver:
         self.sub_edges, self.inter = bucket_edges(part, graph.u, graph.v, graph.w)
         self.B = part.M
         dev = self.device
-        self.batch = QaoaBatch(part.size, self.sub_edges, max_p=cfg.p, max_k=cfg.k, gradient=True, device=dev)
+        self.batch = QaoaBatch(part.size, self.sub_edges, max_p=cfg.p, max_k=cfg.k, gradient=True,
+                               skip_edgeless=skip_edgeless, device=dev)
         P = self.B * cfg.p
         self.theta = torch.zeros(2 * P, dtype=torch.float64, device=dev)   # [gamma | beta]
         self.grad = torch.zeros(2 * P, dtype=torch.float64, device=dev)    # [dgamma | dbeta]
@@ -90,8 +91,7 @@ class Solver:
         nq, off, u, v, w = batch_arrays(self.part.size, self.sub_edges)
         _abi.qaoa_batch_destroy(bt.handle)
         bt.handle = 0
-        flags = _abi.QAOA_FLAG_GRADIENT
-        bt.handle = _abi.qaoa_batch_create(bt.B, nq, off, u, v, w, bt.max_p, bt.max_k, flags,
+        bt.handle = _abi.qaoa_batch_create(bt.B, nq, off, u, v, w, bt.max_p, bt.max_k, bt.flags,
                                            _ptr(bt.workspace), bt.workspace.numel(), _stream(stream))
 
     def set_angles(self, gamma, beta):

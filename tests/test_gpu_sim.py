@@ -227,3 +227,29 @@ def test_edgeless_subgraph_gradient_is_zero():
     E, dg, db = bt.expectation_grad(gamma, beta)
     assert float(E.abs().max()) == 0.0 and float(dg.abs().max()) == 0.0 and float(db.abs().max()) == 0.0
     bt.close()
+
+
+def test_skip_edgeless_matches_simulation():
+    # edgeless subgraphs in closed form: E = 0, gradient 0, top-k = 0, 2, 4, ...
+    sizes = [14, 9, 20, 12]
+    edges = _subgraphs(sizes, 61)
+    edges[1] = (np.zeros(0, np.int32),) * 3
+    edges[2] = (np.zeros(0, np.int32),) * 3
+    gamma, beta = synth.uniform_angles(62, 2, batch=len(sizes))
+    ref = QaoaBatch(sizes, edges, max_p=2, max_k=8, gradient=True)
+    skp = QaoaBatch(sizes, edges, max_p=2, max_k=8, gradient=True, skip_edgeless=True)
+    out = []
+    for bt in (ref, skp):
+        bt.apply_layers(gamma, beta)
+        E = bt.expectation().cpu().numpy()
+        idx, prob = bt.topk(8)
+        Eg, dg, db = bt.expectation_grad(gamma, beta)
+        out.append((E, idx_to_uint32(idx), prob.cpu().numpy(), Eg.cpu().numpy(), dg.cpu().numpy(), db.cpu().numpy()))
+    (E0, i0, p0, Eg0, dg0, db0), (E1, i1, p1, Eg1, dg1, db1) = out
+    assert np.array_equal(E0, E1) and np.array_equal(Eg0, Eg1)
+    assert np.array_equal(dg0, dg1) and np.array_equal(db0, db1)
+    assert np.array_equal(i0, i1)
+    assert np.allclose(p0, p1, rtol=1e-6, atol=0)
+    assert list(i1[1]) == [0, 2, 4, 6, 8, 10, 12, 14]
+    ref.close()
+    skp.close()

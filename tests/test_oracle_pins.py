@@ -496,3 +496,35 @@ def test_cut_decomposition_invariant():
     inside = lambda a, b: any(s <= a < s + n and s <= b < s + n for s, n in zip(start, size))
     inter = sum(int(x[a] != x[b]) for a, b in zip(g.u, g.v) if not inside(a, b))
     assert intra + inter == best == oracle.cutval(g.u, g.v, None, x)
+
+
+# ---------------------------------------------------------------- angle predictor
+def test_mlp_gradient_matches_finite_differences():
+    rng = np.random.default_rng(3)
+    in_dim, H, out = 5, 7, 3
+    npar = oracle.mlp_num_params(in_dim, H, out)
+    assert npar == H * in_dim + H + H * H + H + out * H + out
+    P = rng.normal(0, 0.5, npar)
+    X = rng.normal(0, 1, (6, in_dim))
+    T = rng.normal(0, 1, (6, out))
+    loss, G = oracle.mlp_loss_grad(P, X, T, H)
+    Y = oracle.mlp_forward(P, X, H, out)
+    assert loss == pytest.approx(np.mean((Y - T) ** 2), rel=1e-12)
+    h = 1e-6
+    for i in range(npar):
+        e = np.zeros(npar)
+        e[i] = h
+        fd = (oracle.mlp_loss_grad(P + e, X, T, H)[0] - oracle.mlp_loss_grad(P - e, X, T, H)[0]) / (2 * h)
+        assert abs(G[i] - fd) <= 1e-6 * max(1.0, abs(fd)), i
+
+
+def test_mlp_forward_is_a_relu_network():
+    # a single hidden unit path: with W1 = I-like, W2 = I, W3 = I the output
+    # is relu(relu(x)) = relu(x)
+    in_dim = H = out = 4
+    W1 = np.eye(4)
+    W2 = np.eye(4)
+    W3 = np.eye(4)
+    P = np.concatenate([W1.ravel(), np.zeros(4), W2.ravel(), np.zeros(4), W3.ravel(), np.zeros(4)])
+    X = np.array([[1.0, -2.0, 0.5, -0.1]])
+    assert np.allclose(oracle.mlp_forward(P, X, H, out), np.maximum(X, 0))
