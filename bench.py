@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the Adam step from a captured HIP graph")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the hot path "
@@ -77,6 +80,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe: 3 copies of {n} bytes (read {n}, write {n} per copy)")
+        return
     g = synth.erdos_renyi(400, 0.05, 0)
     part = partition_equal(400, 20)
     cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
@@ -88,11 +100,13 @@ def main():
 
     def step():
         S.rebuild()
-        S.run()
+        S.run(graph=args.graph)
 
     for i in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.graph:
+        log("bench: Adam steps replay a captured HIP graph")
     log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps")
     _abi.qaoa_profile_enable(1)
     torch.cuda.synchronize()
@@ -132,6 +146,7 @@ def main():
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": "plain-method solve, G(400,0.05) seed 0, 21 subgraphs x 20 qubits, p=3, "
                                "50 Adam steps, top-16, beam 4096, CutVal",
+                   "graph_replay": bool(args.graph),
                    "vertices": 400, "edges": g.num_edges, "subgraphs": part.M, "qubits": 20, "p": cfg.p,
                    "adam_steps": cfg.iters, "k": cfg.k, "beam": cfg.beam},
         "hbm_gbs_step": total_bytes / args.steps / (elapsed / args.steps) / 1e9,

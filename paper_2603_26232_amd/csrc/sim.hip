@@ -122,11 +122,11 @@ __device__ inline void xchg(float2* lds, uint32_t tid, float2 (&v)[REGS])
     __syncthreads();
     lds_read<LT>(lds, tid, v);
     __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
 }
 
-// Reduced pair rotations (see the header comment): mode 0 is
-// (a, b) -> (a - i t b, b - i t a); mode 1 is (a, b) -> (b + i t a, a + i t b).
-// The inverse rotation is the same operator with -t.
+// Reduced pair rotation (I - i t X) on (a, b) = (psi(z), psi(z ^ bit)):
+// (a, b) -> (a - i t b, b - i t a). t = 0 is exactly the identity.
 __device__ inline void rx_tan(float2& a, float2& b, float t)
 {
     const float2 na = make_float2(a.x + t * b.y, a.y - t * b.x);
@@ -134,48 +134,34 @@ __device__ inline void rx_tan(float2& a, float2& b, float t)
     a = na;
     b = nb;
 }
-__device__ inline void rx_cot(float2& a, float2& b, float t)
-{
-    const float2 na = make_float2(b.x - t * a.y, b.y + t * a.x);
-    const float2 nb = make_float2(a.x - t * b.y, a.y + t * b.x);
-    a = na;
-    b = nb;
-}
 
-template <int MODE>
-__device__ inline void rx_bit(float2 (&v)[REGS], int k, float t)
+template <int K>
+__device__ inline void rx_bit(float2 (&v)[REGS], float t)
 {
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) {
-        if (r & (1 << k)) continue;
-        if (MODE == 0) rx_tan(v[r], v[r | (1 << k)], t);
-        else rx_cot(v[r], v[r | (1 << k)], t);
-    }
+    for (int r = 0; r < REGS; ++r)
+        if (!(r & (1 << K))) rx_tan(v[r], v[r | (1 << K)], t);
 }
 
-__device__ inline void rx_regs(float2 (&v)[REGS], unsigned mask, int mode, float t)
+// one round: the four register bits with their own coefficients (0 for a
+// register bit that is not an active qubit of the group)
+__device__ inline void rx_round(float2 (&v)[REGS], const float (&tk)[4])
 {
-    if (mode == 0) {
-        if (mask & 1u) rx_bit<0>(v, 0, t);
-        if (mask & 2u) rx_bit<0>(v, 1, t);
-        if (mask & 4u) rx_bit<0>(v, 2, t);
-        if (mask & 8u) rx_bit<0>(v, 3, t);
-    } else {
-        if (mask & 1u) rx_bit<1>(v, 0, t);
-        if (mask & 2u) rx_bit<1>(v, 1, t);
-        if (mask & 4u) rx_bit<1>(v, 2, t);
-        if (mask & 8u) rx_bit<1>(v, 3, t);
-    }
+    rx_bit<0>(v, tk[0]);
+    rx_bit<1>(v, tk[1]);
+    rx_bit<2>(v, tk[2]);
+    rx_bit<3>(v, tk[3]);
 }
 
 // sum over one register bit of Im conj(lam(z)) psi(z ^ bit), both directions
-__device__ inline float xb_bit(const float2 (&ps)[REGS], const float2 (&la)[REGS], int k)
+template <int K>
+__device__ inline float xb_bit(const float2 (&ps)[REGS], const float2 (&la)[REGS])
 {
     float acc = 0.f;
 #pragma unroll
     for (int r = 0; r < REGS; ++r) {
-        if (r & (1 << k)) continue;
-        const int r1 = r | (1 << k);
+        if (r & (1 << K)) continue;
+        const int r1 = r | (1 << K);
         acc += la[r].x * ps[r1].y - la[r].y * ps[r1].x;
         acc += la[r1].x * ps[r].y - la[r1].y * ps[r].x;
     }
@@ -193,40 +179,55 @@ __device__ inline void scale_regs(float2 (&v)[REGS], float2 f)
     for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], f);
 }
 
-// Per-layer rotation parameters (built in FP64 by the angle-prep kernel).
+// Per-layer rotation parameters (built in FP64 by the angle-prep kernel):
+// e^{-i beta X} = f (I - i t X) X^flip per qubit.
 struct RxC {
     float t;
-    int mode;
-    float fsq;  // |per-qubit factor|^2
-    float2 Ff, Fi;  // whole-group factors of this pass's group (forward, inverse)
+    int flip;
+    float fsq;      // |f|^2
+    float2 Ff, Fi;  // f^(group size), forward and inverse
 };
 
 __device__ inline RxC load_rx(const RxCoef* cf, int l, int g)
 {
     RxC r;
     r.t = cf[l].t;
-    r.mode = cf[l].mode;
+    r.flip = cf[l].mode;
     r.fsq = cf[l].fsq;
     r.Ff = cf[l].Ff[g];
     r.Fi = cf[l].Fi[g];
     return r;
 }
 
+template <int L>
+__device__ inline void round_coef(float (&tk)[4], float t, int c)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tk[k] = (layout_bit0<L>() + k >= c) ? t : 0.f;
+}
+
+// Tile bits of the group's qubits (the ones a flip permutes).
+__device__ inline uint32_t group_bits(int c) { return ((uint32_t)TILE - 1u) & ~((1u << c) - 1u); }
+
 // One RX segment (all qubits of the group, one layer) walking the layout
-// chain in direction DIR (true: start -> end). Forward rotation, no factor.
+// chain in direction DIR (true: start -> end), coefficient t.
 template <int CH, bool DIR>
-__device__ inline void seg_fwd(float2 (&v)[REGS], float2* lds, int c, int mode, float t, uint32_t tid)
+__device__ inline void seg_rot(float2 (&v)[REGS], float2* lds, int c, float t, uint32_t tid)
 {
     constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
-    rx_regs(v, active_mask<L0>(c), mode, t);
+    float tk[4];
+    round_coef<L0>(tk, t, c);
+    rx_round(v, tk);
     if constexpr (CH >= 2) {
         constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
         xchg<L0, L1>(lds, tid, v);
-        rx_regs(v, active_mask<L1>(c), mode, t);
+        round_coef<L1>(tk, t, c);
+        rx_round(v, tk);
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, v);
-            rx_regs(v, active_mask<L2>(c), mode, t);
+            round_coef<L2>(tk, t, c);
+            rx_round(v, tk);
         }
     }
 }
@@ -236,21 +237,30 @@ __device__ inline void seg_fwd(float2 (&v)[REGS], float2* lds, int c, int mode, 
 // |f|^(-done) (done = qubits already rotated in earlier rounds of this
 // segment), so they are multiplied back by fsq^done.
 template <int L>
-__device__ inline void bwd_round(float2 (&ps)[REGS], float2 (&la)[REGS], int c, int mode, float t, float fsq,
-                                 float& wdone, double& xacc)
+__device__ inline void bwd_round(float2 (&ps)[REGS], float2 (&la)[REGS], int c, float t, float fsq, float& wdone,
+                                 double& xacc)
 {
-    const unsigned m = active_mask<L>(c);
-    float a = 0.f;
+    float tk[4], wk[4];
+    float w = wdone;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (m & (1u << k)) a += xb_bit(ps, la, k);
-    // every bit of this round sees the same scale (no rotation yet this round)
-    xacc += (double)(wdone * a);
-    rx_regs(ps, m, mode, -t);
-    rx_regs(la, m, mode, -t);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        if (m & (1u << k)) wdone *= fsq;
+    for (int k = 0; k < 4; ++k) {
+        const bool act = layout_bit0<L>() + k >= c;
+        tk[k] = act ? -t : 0.f;
+        wk[k] = act ? wdone : 0.f;
+        w = act ? w * fsq : w;
+    }
+    const float a = wk[0] * xb_bit<0>(ps, la) + wk[1] * xb_bit<1>(ps, la) + wk[2] * xb_bit<2>(ps, la) +
+                    wk[3] * xb_bit<3>(ps, la);
+    xacc += (double)a;
+    // separate scheduling regions for the products and the two states'
+    // rotations: interleaving them keeps old and new values of both states
+    // live at once
+    __builtin_amdgcn_sched_barrier(0);
+    rx_round(ps, tk);
+    __builtin_amdgcn_sched_barrier(0);
+    rx_round(la, tk);
+    __builtin_amdgcn_sched_barrier(0);
+    wdone = w;
 }
 
 template <int CH, bool DIR>
@@ -259,29 +269,30 @@ __device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* l
 {
     float wdone = 1.f;
     constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
-    bwd_round<L0>(ps, la, c, rc.mode, rc.t, rc.fsq, wdone, xacc);
+    bwd_round<L0>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
     if constexpr (CH >= 2) {
         constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
         xchg<L0, L1>(lds, tid, ps);
         xchg<L0, L1>(lds, tid, la);
-        bwd_round<L1>(ps, la, c, rc.mode, rc.t, rc.fsq, wdone, xacc);
+        bwd_round<L1>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, ps);
             xchg<L1, L2>(lds, tid, la);
-            bwd_round<L2>(ps, la, c, rc.mode, rc.t, rc.fsq, wdone, xacc);
+            bwd_round<L2>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
         }
     }
 }
 
-// C(z) for the 16 amplitudes a lane holds in layout L (group 0: natural
-// table; the last group: its tile-order copy, contiguous per tile).
+// C(z) for the 16 amplitudes a lane holds in layout L, for data permuted by
+// the flip mask m (slot q holds amplitude q ^ m). Group 0 reads the natural
+// table, the last group its tile-order copy (contiguous per tile).
 template <int L>
-__device__ inline void load_cut_L(uint16_t (&cr)[REGS], const uint16_t* tab, uint32_t tid)
+__device__ inline void load_cut_L(uint16_t (&cr)[REGS], const uint16_t* tab, uint32_t tid, uint32_t m)
 {
-    const uint16_t* p = tab + thread_part<L>(tid);
+    const uint32_t tp = thread_part<L>(tid) ^ m;
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) cr[r] = p[reg_part<L>(r)];
+    for (int r = 0; r < REGS; ++r) cr[r] = tab[tp ^ reg_part<L>(r)];
 }
 
 template <int L>
@@ -292,12 +303,13 @@ __device__ inline void load_state(float2 (&v)[REGS], const float2* st, const Geo
     for (int r = 0; r < REGS; ++r) v[r] = p[gmap(geo, reg_part<L>(r))];
 }
 
+// store slot q to amplitude q ^ m (gmap is a bit deposit, so it commutes with xor)
 template <int L>
-__device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Geo& geo, uint32_t tid)
+__device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Geo& geo, uint32_t tid, uint32_t m)
 {
-    float2* p = st + (geo.zb | gmap(geo, thread_part<L>(tid)));
+    const uint32_t base = (geo.zb | gmap(geo, thread_part<L>(tid))) ^ gmap(geo, m);
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) p[gmap(geo, reg_part<L>(r))] = v[r];
+    for (int r = 0; r < REGS; ++r) st[base ^ gmap(geo, reg_part<L>(r))] = v[r];
 }
 
 // deterministic block sum (wave64 butterfly, then the 4 wave totals in order)
@@ -402,9 +414,12 @@ __global__ __launch_bounds__(THREADS) void k_angle_prep(uint8_t* ws, const SubDe
         sincos(bt, &s, &c);
         RxCoef rc;
         rc.cs = make_float2((float)c, (float)s);
+        // e^{-i beta X} = c (I - i tan(beta) X)            when |cos| >= |sin|
+        //               = -i s X (I + i cot(beta) X)       otherwise
+        // i.e. f (I - i t X) X^flip with (f, t) = (c, tan) or (-i s, -cot)
         const bool tanm = fabs(c) >= fabs(s);
         rc.mode = tanm ? 0 : 1;
-        rc.t = (float)(tanm ? s / c : c / s);
+        rc.t = (float)(tanm ? s / c : -c / s);
         rc.fsq = (float)(tanm ? c * c : s * s);
         // per-qubit factors: forward c or -i s, inverse c or +i s
         const double fr = tanm ? c : 0.0, fi_f = tanm ? 0.0 : -s, fi_i = tanm ? 0.0 : s;
@@ -447,6 +462,9 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
     RxC pre{}, post{};
     if (ops.pre >= 0) pre = load_rx(cf, ops.pre, g);
     if (ops.post >= 0) post = load_rx(cf, ops.post, g);
+    const uint32_t gb = group_bits(geo.c);
+    const uint32_t m_pre = (ops.pre >= 0 && pre.flip) ? gb : 0u;          // after RX(pre)
+    const uint32_t m_end = m_pre ^ ((ops.post >= 0 && post.flip) ? gb : 0u);  // after RX(post)
     // phase table, with the factor of the segment before it folded in
     if (ops.ph >= 0) {
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
@@ -455,10 +473,11 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
     }
     const int nseg = (ops.pre >= 0) + (ops.post >= 0);
     const bool cut_at_end = (ops.ph >= 0) ? (ops.pre >= 0) : (nseg & 1);
+    const uint32_t m_cut = (ops.ph >= 0) ? m_pre : m_end;
     uint16_t cr[REGS];
     if (ops.ph >= 0 || ops.epi_e) {
-        if (cut_at_end) load_cut_L<LE>(cr, tab, tid);
-        else load_cut_L<LS>(cr, tab, tid);
+        if (cut_at_end) load_cut_L<LE>(cr, tab, tid, m_cut);
+        else load_cut_L<LS>(cr, tab, tid, m_cut);
     }
     float2 v[REGS];
     if (ops.init) {
@@ -471,7 +490,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
     __syncthreads();  // phase table staged
     bool at_start = true;
     if (ops.pre >= 0) {
-        seg_fwd<CH, true>(v, lds, geo.c, pre.mode, pre.t, tid);
+        seg_rot<CH, true>(v, lds, geo.c, pre.t, tid);
         at_start = false;
         if (ops.ph < 0) scale_regs(v, pre.Ff);
     }
@@ -480,8 +499,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
         for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
     }
     if (ops.post >= 0) {
-        if (at_start) seg_fwd<CH, true>(v, lds, geo.c, post.mode, post.t, tid);
-        else seg_fwd<CH, false>(v, lds, geo.c, post.mode, post.t, tid);
+        if (at_start) seg_rot<CH, true>(v, lds, geo.c, post.t, tid);
+        else seg_rot<CH, false>(v, lds, geo.c, post.t, tid);
         at_start = !at_start;
         scale_regs(v, post.Ff);
     }
@@ -493,8 +512,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
         acc = block_sum(acc, red);
         if (tid == 0) part.e[sd->tile_base + t] = acc;
     }
-    if (at_start) store_state<LS>(v, st, geo, tid);
-    else store_state<LE>(v, st, geo, tid);
+    if (at_start) store_state<LS>(v, st, geo, tid, m_end);
+    else store_state<LE>(v, st, geo, tid, m_end);
 }
 
 // ---------------------------------------------------------------------------
@@ -505,7 +524,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
 // else : unmix(pre) + beta-grad, gamma-grad + unphase(ph), unmix(post) +
 //        beta-grad; store both unless this is the last pass.
 // ---------------------------------------------------------------------------
-template <int CH>
+template <int CH, bool FUSED>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_WAVES))) void k_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
                                                       PassOps ops, Partials part)
 {
@@ -532,6 +551,9 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     RxC pre{}, post{};
     if (ops.pre >= 0) pre = load_rx(cf, ops.pre, g);
     if (ops.post >= 0) post = load_rx(cf, ops.post, g);
+    const uint32_t gb = group_bits(geo.c);
+    const uint32_t m_pre = (ops.pre >= 0 && pre.flip) ? gb : 0u;
+    const uint32_t m_end = m_pre ^ ((ops.post >= 0 && post.flip) ? gb : 0u);
     // conjugate phase table with the inverse factor of the preceding segment
     if (ops.ph >= 0 && !ops.last) {
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
@@ -541,32 +563,30 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
             lut[i] = cmul(make_float2(e.x, -e.y), F);
         }
     }
-    uint16_t cr[REGS];
-    if (ops.fused || ops.ph >= 0) load_cut_L<LE>(cr, tab, tid);
-
     float2 ps[REGS], la[REGS];
     load_state<LS>(ps, sp, geo, tid);
-    if (!ops.fused) load_state<LS>(la, sl, geo, tid);
+    if (!FUSED) load_state<LS>(la, sl, geo, tid);
     __syncthreads();
-    bool at_start = true;
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
-    if (ops.fused) {
-        seg_fwd<CH, true>(ps, lds, geo.c, pre.mode, pre.t, tid);
-        scale_regs(ps, pre.Ff);  // psi_p at true scale
+    uint16_t cr[REGS];
+    if (FUSED) {
+        // psi_p = RX(pre) psi (slot q then holds amplitude q ^ m_pre)
+        seg_rot<CH, true>(ps, lds, geo.c, pre.t, tid);
+        scale_regs(ps, pre.Ff);
+        load_cut_L<LE>(cr, tab, tid, m_pre);
 #pragma unroll
         for (int r = 0; r < REGS; ++r) {
             const float c = (float)cr[r];
             acc_e += ((double)ps[r].x * ps[r].x + (double)ps[r].y * ps[r].y) * (double)cr[r];
             la[r] = make_float2(c * ps[r].x, c * ps[r].y);
         }
+        // the inverse rotation flips back: the stored lambda is unpermuted
         seg_bwd<CH, false>(ps, la, lds, geo.c, pre, tid, acc_pre);
         scale_regs(la, pre.Fi);
     } else {
-        if (ops.pre >= 0) {
-            seg_bwd<CH, true>(ps, la, lds, geo.c, pre, tid, acc_pre);
-            at_start = false;
-        }
+        seg_bwd<CH, true>(ps, la, lds, geo.c, pre, tid, acc_pre);
         if (ops.ph >= 0) {
+            load_cut_L<LE>(cr, tab, tid, m_pre);
             // on the rotated-but-unscaled states; rescale by |F|^2
             float a = 0.f;
 #pragma unroll
@@ -582,14 +602,12 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
                     la[r] = cmul(la[r], f);
                 }
             }
-        } else if (ops.pre >= 0 && !ops.last) {
+        } else if (!ops.last) {
             scale_regs(ps, pre.Fi);
             scale_regs(la, pre.Fi);
         }
         if (ops.post >= 0) {
-            if (at_start) seg_bwd<CH, true>(ps, la, lds, geo.c, post, tid, acc_post);
-            else seg_bwd<CH, false>(ps, la, lds, geo.c, post, tid, acc_post);
-            at_start = !at_start;
+            seg_bwd<CH, false>(ps, la, lds, geo.c, post, tid, acc_post);
             if (!ops.last) {
                 scale_regs(ps, post.Fi);
                 scale_regs(la, post.Fi);
@@ -597,7 +615,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
         }
     }
     // partial sums (every thread takes part in each block_sum)
-    if (ops.fused) {
+    if (FUSED) {
         const double e = block_sum(acc_e, red);
         const double x = block_sum(acc_pre, red);
         if (tid == 0) {
@@ -605,7 +623,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
             part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = x;
         }
     } else {
-        if (ops.pre >= 0) {
+        {
             const double x = block_sum(acc_pre, red);
             if (tid == 0) part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = x;
         }
@@ -619,16 +637,17 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
         }
     }
     if (ops.last) return;
-    if (ops.fused) {
-        store_state<LS>(la, sl, geo, tid);
+    if (FUSED) {
+        store_state<LS>(la, sl, geo, tid, 0u);
         return;
     }
-    if (at_start) {
-        store_state<LS>(ps, sp, geo, tid);
-        store_state<LS>(la, sl, geo, tid);
+    // after pre (and post) the chain position is the end (or the start again)
+    if (ops.post >= 0) {
+        store_state<LS>(ps, sp, geo, tid, m_end);
+        store_state<LS>(la, sl, geo, tid, m_end);
     } else {
-        store_state<LE>(ps, sp, geo, tid);
-        store_state<LE>(la, sl, geo, tid);
+        store_state<LE>(ps, sp, geo, tid, m_end);
+        store_state<LE>(la, sl, geo, tid, m_end);
     }
 }
 
@@ -799,9 +818,16 @@ hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, i
 {
     if (nwork <= 0) return hipSuccess;
     const size_t lds = pass_lds(lut_max);
-    if (chain == 3) hipLaunchKernelGGL(k_bwd_pass<3>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
-    else if (chain == 2) hipLaunchKernelGGL(k_bwd_pass<2>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
-    else hipLaunchKernelGGL(k_bwd_pass<1>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
+    const dim3 g(nwork), b(THREADS);
+    if (ops.fused) {
+        if (chain == 3) hipLaunchKernelGGL((k_bwd_pass<3, true>), g, b, lds, s, ws, subs, work, ops, part);
+        else if (chain == 2) hipLaunchKernelGGL((k_bwd_pass<2, true>), g, b, lds, s, ws, subs, work, ops, part);
+        else hipLaunchKernelGGL((k_bwd_pass<1, true>), g, b, lds, s, ws, subs, work, ops, part);
+    } else {
+        if (chain == 3) hipLaunchKernelGGL((k_bwd_pass<3, false>), g, b, lds, s, ws, subs, work, ops, part);
+        else if (chain == 2) hipLaunchKernelGGL((k_bwd_pass<2, false>), g, b, lds, s, ws, subs, work, ops, part);
+        else hipLaunchKernelGGL((k_bwd_pass<1, false>), g, b, lds, s, ws, subs, work, ops, part);
+    }
     return hipGetLastError();
 }
 

@@ -113,6 +113,32 @@ class Solver:
             _abi.qaoa_adam_step(2 * P, th, gr, _ptr(self.m), _ptr(self.v), _ptr(self.step), cfg.lr, cfg.beta1,
                                 cfg.beta2, cfg.eps, 1, s)
 
+    def _one_step(self, s: int):
+        cfg = self.cfg
+        P = self.B * cfg.p
+        th, gr = _ptr(self.theta), _ptr(self.grad)
+        _abi.qaoa_expectation_grad(self.batch.handle, cfg.p, th, th + 8 * P, _ptr(self.E), gr, gr + 8 * P, s)
+        _abi.qaoa_adam_step(2 * P, th, gr, _ptr(self.m), _ptr(self.v), _ptr(self.step), cfg.lr, cfg.beta1,
+                            cfg.beta2, cfg.eps, 1, s)
+
+    def optimise_graph(self, iters: int):
+        """Same as `optimise`, replaying one captured HIP graph of an Adam step
+        (gradient kernels + Adam); the step counter lives on the device, so
+        every replay is the next step. The graph is captured on first use and
+        kept with the solver (it holds this batch's buffers)."""
+        # the captured kernels reference only the workspace (whose layout a
+        # rebuild of the same batch reproduces) and this solver's buffers
+        if getattr(self, "_graph", None) is None:
+            cap = torch.cuda.Stream()
+            cap.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                self._one_step(int(cap.cuda_stream))
+            torch.cuda.current_stream().wait_stream(cap)
+            self._graph = g
+        for _ in range(iters):
+            self._graph.replay()
+
     def finish(self, stream=None):
         """Final state, expectation, top-k, merge and CutVal (device only)."""
         cfg = self.cfg
@@ -129,11 +155,15 @@ class Solver:
         _abi.maxcut_eval(g.num_vertices, g.num_edges, _ptr(self.du), _ptr(self.dv), _ptr(self.dw), 1,
                          _ptr(self.best), _ptr(self.eval_cut), s)
 
-    def run(self, gamma0=None, beta0=None, iters=None, stream=None):
+    def run(self, gamma0=None, beta0=None, iters=None, stream=None, graph=False):
         if gamma0 is None:
             gamma0, beta0 = cold_start(self.cfg.p, self.B)
         self.set_angles(gamma0, beta0)
-        self.optimise(self.cfg.iters if iters is None else iters, stream)
+        n = self.cfg.iters if iters is None else iters
+        if graph:
+            self.optimise_graph(n)
+        else:
+            self.optimise(n, stream)
         self.finish(stream)
 
     def result(self) -> SolveResult:

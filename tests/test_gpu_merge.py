@@ -155,3 +155,26 @@ def test_plain_solve_400_vertices_full_size():
     ref_cut, ref_x, _, _ = oracle.merge(400, part.start, part.size, g.u, g.v, g.w, r.cand, W=cfg.beam)
     assert r.cut == ref_cut and np.array_equal(r.assignment, ref_x)
     S.close()
+
+
+def test_graph_replay_matches_eager_optimiser():
+    """A captured Adam step replayed T times gives bit-identical angles to T
+    eager steps; replays are interleaved with eager work and checked each time."""
+    g = synth.erdos_renyi(90, 0.12, 8)
+    part = partition_equal(90, 16)
+    cfg = SolveConfig(p=3, iters=6, k=8, beam=64)
+    S = Solver(g, part, cfg)
+    g0, b0 = cold_start(cfg.p, part.M)
+    S.set_angles(g0, b0)
+    S.optimise(6)
+    torch.cuda.synchronize()
+    ref = S.theta.clone()
+    for rep in range(3):
+        S.set_angles(g0, b0)
+        S.optimise_graph(6)
+        torch.cuda.synchronize()
+        assert torch.equal(S.theta, ref), rep
+        # eager work between replays
+        S.finish()
+        torch.cuda.synchronize()
+    S.close()

@@ -248,8 +248,14 @@ def test_skip_edgeless_matches_simulation():
     (E0, i0, p0, Eg0, dg0, db0), (E1, i1, p1, Eg1, dg1, db1) = out
     assert np.array_equal(E0, E1) and np.array_equal(Eg0, Eg1)
     assert np.array_equal(dg0, dg1) and np.array_equal(db0, db1)
-    assert np.array_equal(i0, i1)
-    assert np.allclose(p0, p1, rtol=1e-6, atol=0)
-    assert list(i1[1]) == [0, 2, 4, 6, 8, 10, 12, 14]
+    # subgraphs with edges: identical; edgeless ones: the simulated
+    # probabilities tie up to FP32 rounding (any order is acceptable), the
+    # closed form breaks the exact tie by index
+    for b in (0, 3):
+        assert np.array_equal(i0[b], i1[b]) and np.array_equal(p0[b], p1[b])
+    for b, n in ((1, 9), (2, 20)):
+        assert list(i1[b]) == [0, 2, 4, 6, 8, 10, 12, 14]
+        assert np.all(p1[b] == np.float32(2.0 ** -n))
+        assert np.allclose(p0[b], 2.0 ** -n, rtol=1e-5, atol=0) and np.all(i0[b] % 2 == 0)
     ref.close()
     skp.close()
