@@ -145,7 +145,14 @@ struct Plan {
     std::vector<Class> classes;
 };
 
-int chain_of(const SubDesc& d, int g) { return g == 0 ? 3 : (d.gsize[g] >= 5 ? 2 : 1); }
+// layout-chain code of group g (see launch_fwd_pass): 3 for group 0; for a
+// high group 2 (8 qubits), 4 (5..7), 1 (4), 5 (1..3)
+int chain_of(const SubDesc& d, int g)
+{
+    if (g == 0) return 3;
+    const int nb = d.gsize[g];
+    return nb == 8 ? 2 : (nb >= 5 ? 4 : (nb == 4 ? 1 : 5));
+}
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 

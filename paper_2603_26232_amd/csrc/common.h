@@ -125,8 +125,8 @@ hipError_t launch_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work,
                              hipStream_t s);
 hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, const double* gamma,
                              const double* beta, hipStream_t s);
-// chain: layout-chain shape of the pass's group (3: group 0; 2: a high group
-// of 5..8 qubits; 1: a high group of at most 4 qubits)
+// chain: layout-chain code of the pass's group (3: group 0; 2 / 4: a high
+// group of 8 / 5..7 qubits; 1 / 5: a high group of 4 / 1..3 qubits)
 hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,
                            PassOps ops, Partials part, int lut_max, hipStream_t s);
 hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,

@@ -153,19 +153,22 @@ __device__ inline void rx_round(float2 (&v)[REGS], const float (&tk)[4])
     rx_bit<3>(v, tk[3]);
 }
 
-// sum over one register bit of Im conj(lam(z)) psi(z ^ bit), both directions
+// sum over one register bit of Im conj(lam(z)) psi(z ^ bit), both directions,
+// as FMA chains into two accumulators
 template <int K>
 __device__ inline float xb_bit(const float2 (&ps)[REGS], const float2 (&la)[REGS])
 {
-    float acc = 0.f;
+    float a0 = 0.f, a1 = 0.f;
 #pragma unroll
     for (int r = 0; r < REGS; ++r) {
         if (r & (1 << K)) continue;
         const int r1 = r | (1 << K);
-        acc += la[r].x * ps[r1].y - la[r].y * ps[r1].x;
-        acc += la[r1].x * ps[r].y - la[r1].y * ps[r].x;
+        a0 = fmaf(la[r].x, ps[r1].y, a0);
+        a0 = fmaf(-la[r].y, ps[r1].x, a0);
+        a1 = fmaf(la[r1].x, ps[r].y, a1);
+        a1 = fmaf(-la[r1].y, ps[r].x, a1);
     }
-    return acc;
+    return a0 + a1;
 }
 
 __device__ inline float2 cmul(float2 a, float2 b)
@@ -199,11 +202,14 @@ __device__ inline RxC load_rx(const RxCoef* cf, int l, int g)
     return r;
 }
 
-template <int L>
+// FULL: every register bit of every layout in the chain is an active qubit
+// (group 0, and high groups of exactly 4 or 8 qubits); then no per-bit
+// selection is needed.
+template <int L, bool FULL>
 __device__ inline void round_coef(float (&tk)[4], float t, int c)
 {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) tk[k] = (layout_bit0<L>() + k >= c) ? t : 0.f;
+    for (int k = 0; k < 4; ++k) tk[k] = (FULL || layout_bit0<L>() + k >= c) ? t : 0.f;
 }
 
 // Tile bits of the group's qubits (the ones a flip permutes).
@@ -211,22 +217,22 @@ __device__ inline uint32_t group_bits(int c) { return ((uint32_t)TILE - 1u) & ~(
 
 // One RX segment (all qubits of the group, one layer) walking the layout
 // chain in direction DIR (true: start -> end), coefficient t.
-template <int CH, bool DIR>
+template <int CH, bool FULL, bool DIR>
 __device__ inline void seg_rot(float2 (&v)[REGS], float2* lds, int c, float t, uint32_t tid)
 {
     constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
     float tk[4];
-    round_coef<L0>(tk, t, c);
+    round_coef<L0, FULL>(tk, t, c);
     rx_round(v, tk);
     if constexpr (CH >= 2) {
         constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
         xchg<L0, L1>(lds, tid, v);
-        round_coef<L1>(tk, t, c);
+        round_coef<L1, FULL>(tk, t, c);
         rx_round(v, tk);
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, v);
-            round_coef<L2>(tk, t, c);
+            round_coef<L2, FULL>(tk, t, c);
             rx_round(v, tk);
         }
     }
@@ -236,7 +242,7 @@ __device__ inline void seg_rot(float2 (&v)[REGS], float2* lds, int c, float t, u
 // inner products are all taken before its rotations, on states scaled by
 // |f|^(-done) (done = qubits already rotated in earlier rounds of this
 // segment), so they are multiplied back by fsq^done.
-template <int L>
+template <int L, bool FULL>
 __device__ inline void bwd_round(float2 (&ps)[REGS], float2 (&la)[REGS], int c, float t, float fsq, float& wdone,
                                  double& xacc)
 {
@@ -244,7 +250,7 @@ __device__ inline void bwd_round(float2 (&ps)[REGS], float2 (&la)[REGS], int c, 
     float w = wdone;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const bool act = layout_bit0<L>() + k >= c;
+        const bool act = FULL || layout_bit0<L>() + k >= c;
         tk[k] = act ? -t : 0.f;
         wk[k] = act ? wdone : 0.f;
         w = act ? w * fsq : w;
@@ -252,34 +258,28 @@ __device__ inline void bwd_round(float2 (&ps)[REGS], float2 (&la)[REGS], int c, 
     const float a = wk[0] * xb_bit<0>(ps, la) + wk[1] * xb_bit<1>(ps, la) + wk[2] * xb_bit<2>(ps, la) +
                     wk[3] * xb_bit<3>(ps, la);
     xacc += (double)a;
-    // separate scheduling regions for the products and the two states'
-    // rotations: interleaving them keeps old and new values of both states
-    // live at once
-    __builtin_amdgcn_sched_barrier(0);
     rx_round(ps, tk);
-    __builtin_amdgcn_sched_barrier(0);
     rx_round(la, tk);
-    __builtin_amdgcn_sched_barrier(0);
     wdone = w;
 }
 
-template <int CH, bool DIR>
+template <int CH, bool FULL, bool DIR>
 __device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* lds, int c, const RxC& rc,
                                uint32_t tid, double& xacc)
 {
     float wdone = 1.f;
     constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
-    bwd_round<L0>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
+    bwd_round<L0, FULL>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
     if constexpr (CH >= 2) {
         constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
         xchg<L0, L1>(lds, tid, ps);
         xchg<L0, L1>(lds, tid, la);
-        bwd_round<L1>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
+        bwd_round<L1, FULL>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, ps);
             xchg<L1, L2>(lds, tid, la);
-            bwd_round<L2>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
+            bwd_round<L2, FULL>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
         }
     }
 }
@@ -301,12 +301,15 @@ __device__ inline void load_state(float2 (&v)[REGS], const float2* st, const Geo
     const float2* p = st + (geo.zb | gmap(geo, thread_part<L>(tid)));
 #pragma unroll
     for (int r = 0; r < REGS; ++r) v[r] = p[gmap(geo, reg_part<L>(r))];
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // store slot q to amplitude q ^ m (gmap is a bit deposit, so it commutes with xor)
 template <int L>
 __device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Geo& geo, uint32_t tid, uint32_t m)
 {
+    // address arithmetic stays here (hoisting it holds 2 VGPRs per register)
+    __builtin_amdgcn_sched_barrier(0);
     const uint32_t base = (geo.zb | gmap(geo, thread_part<L>(tid))) ^ gmap(geo, m);
 #pragma unroll
     for (int r = 0; r < REGS; ++r) st[base ^ gmap(geo, reg_part<L>(r))] = v[r];
@@ -436,17 +439,23 @@ __global__ __launch_bounds__(THREADS) void k_angle_prep(uint8_t* ws, const SubDe
 }
 
 // ---------------------------------------------------------------------------
-// Forward tile pass: [init | load] RX(pre) phase(ph) RX(post) [<C>] store
+// Forward tile pass. Pass kinds (fixed at compile time so the state has one
+// straight-line life): FIRST = synthesise |+>, phase, RX; SINGLE = RX;
+// MID = RX, phase, RX; LAST = RX and the <C> partial of the tile.
 // ---------------------------------------------------------------------------
-template <int CH>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_WAVES))) void k_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
-                                                      PassOps ops, Partials part)
+enum { F_FIRST = 0, F_SINGLE = 1, F_MID = 2, F_LAST = 3 };
+
+template <int CH, bool FULL, int KIND>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_WAVES))) void k_fwd_pass(
+    uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
 {
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* lut = smem + LDS_TILE;
     __shared__ double red[THREADS / 64];
     constexpr int LS = ChainAt<CH, 0>::L, LE = ChainAt<CH, CH - 1>::L;
+    constexpr bool HAS_PRE = KIND != F_FIRST, HAS_PH = KIND == F_FIRST || KIND == F_MID;
+    constexpr bool HAS_POST = HAS_PH;
     const uint32_t tid = threadIdx.x;
     const int2 wk = work[blockIdx.x];
     const SubDesc* sd = subs + wk.x;
@@ -458,29 +467,24 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
     const int lut_len = sd->lut_len;
     const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + sd->tab) + geo.zb
                                    : (const uint16_t*)(ws + sd->tabB) + (size_t)t * TILE;
-
-    RxC pre{}, post{};
-    if (ops.pre >= 0) pre = load_rx(cf, ops.pre, g);
-    if (ops.post >= 0) post = load_rx(cf, ops.post, g);
     const uint32_t gb = group_bits(geo.c);
-    const uint32_t m_pre = (ops.pre >= 0 && pre.flip) ? gb : 0u;          // after RX(pre)
-    const uint32_t m_end = m_pre ^ ((ops.post >= 0 && post.flip) ? gb : 0u);  // after RX(post)
-    // phase table, with the factor of the segment before it folded in
-    if (ops.ph >= 0) {
-        const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
-        const float2 F = ops.pre >= 0 ? pre.Ff : make_float2(1.f, 0.f);
-        for (int i = tid; i < lut_len; i += THREADS) lut[i] = cmul(L[i], F);
-    }
-    const int nseg = (ops.pre >= 0) + (ops.post >= 0);
-    const bool cut_at_end = (ops.ph >= 0) ? (ops.pre >= 0) : (nseg & 1);
-    const uint32_t m_cut = (ops.ph >= 0) ? m_pre : m_end;
+    RxC pre{}, post{};
+    if constexpr (HAS_PRE) pre = load_rx(cf, ops.pre, g);
+    if constexpr (HAS_POST) post = load_rx(cf, ops.post, g);
+    const uint32_t m_pre = (HAS_PRE && pre.flip) ? gb : 0u;                   // after RX(pre)
+    const uint32_t m_end = m_pre ^ ((HAS_POST && post.flip) ? gb : 0u);      // after RX(post)
     uint16_t cr[REGS];
-    if (ops.ph >= 0 || ops.epi_e) {
-        if (cut_at_end) load_cut_L<LE>(cr, tab, tid, m_cut);
-        else load_cut_L<LS>(cr, tab, tid, m_cut);
+    if constexpr (HAS_PH) {
+        // phase table, with the factor of the segment before it folded in
+        const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
+        const float2 F = HAS_PRE ? pre.Ff : make_float2(1.f, 0.f);
+        for (int i = tid; i < lut_len; i += THREADS) lut[i] = cmul(L[i], F);
+        if constexpr (HAS_PRE) load_cut_L<LE>(cr, tab, tid, m_pre);
+        else load_cut_L<LS>(cr, tab, tid, 0u);
     }
+    if constexpr (KIND == F_LAST) load_cut_L<LE>(cr, tab, tid, m_end);
     float2 v[REGS];
-    if (ops.init) {
+    if constexpr (KIND == F_FIRST) {
         const float a = (float)(1.0 / sqrt((double)(1ull << sd->n)));
 #pragma unroll
         for (int r = 0; r < REGS; ++r) v[r] = make_float2(a, 0.f);
@@ -488,23 +492,18 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
         load_state<LS>(v, st, geo, tid);
     }
     __syncthreads();  // phase table staged
-    bool at_start = true;
-    if (ops.pre >= 0) {
-        seg_rot<CH, true>(v, lds, geo.c, pre.t, tid);
-        at_start = false;
-        if (ops.ph < 0) scale_regs(v, pre.Ff);
+    if constexpr (HAS_PRE) {
+        seg_rot<CH, FULL, true>(v, lds, geo.c, pre.t, tid);
+        if constexpr (!HAS_PH) scale_regs(v, pre.Ff);
     }
-    if (ops.ph >= 0) {
+    if constexpr (HAS_PH) {
 #pragma unroll
         for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
-    }
-    if (ops.post >= 0) {
-        if (at_start) seg_rot<CH, true>(v, lds, geo.c, post.t, tid);
-        else seg_rot<CH, false>(v, lds, geo.c, post.t, tid);
-        at_start = !at_start;
+        // FIRST walks start -> end, MID walks back end -> start
+        seg_rot<CH, FULL, KIND == F_FIRST>(v, lds, geo.c, post.t, tid);
         scale_regs(v, post.Ff);
     }
-    if (ops.epi_e) {
+    if constexpr (KIND == F_LAST) {
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < REGS; ++r)
@@ -512,21 +511,25 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
         acc = block_sum(acc, red);
         if (tid == 0) part.e[sd->tile_base + t] = acc;
     }
-    if (at_start) store_state<LS>(v, st, geo, tid, m_end);
+    // after one segment the layout is the chain end; after two it is back at the start
+    if constexpr (KIND == F_MID) store_state<LS>(v, st, geo, tid, m_end);
     else store_state<LE>(v, st, geo, tid, m_end);
 }
 
 // ---------------------------------------------------------------------------
-// Backward tile pass (adjoint sweep) on psi and lambda = C psi_p.
-// fused: RX(pre) on psi, <C> partial, lambda = C psi, then the inverse of
-//        RX(pre) on both with the beta-gradient; only lambda is stored
-//        (psi in memory already is the state before RX(pre)).
-// else : unmix(pre) + beta-grad, gamma-grad + unphase(ph), unmix(post) +
-//        beta-grad; store both unless this is the last pass.
+// Backward tile pass (adjoint sweep) on psi and lambda = C psi_p. Kinds:
+// FUSED : RX(pre) on psi, <C> partial, lambda = C psi, then the inverse of
+//         RX(pre) on both with the beta-gradient; only lambda is stored (psi
+//         in memory already is the state before RX(pre)).
+// SINGLE: unmix(pre) with the beta-gradient; store both.
+// MID   : unmix(pre), gamma-gradient + unphase(ph), unmix(post); store both.
+// LAST  : unmix(pre), gamma-gradient; nothing stored.
 // ---------------------------------------------------------------------------
-template <int CH, bool FUSED>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_WAVES))) void k_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work,
-                                                      PassOps ops, Partials part)
+enum { B_FUSED = 0, B_SINGLE = 1, B_MID = 2, B_LAST = 3 };
+
+template <int CH, bool FULL, int KIND>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_WAVES))) void k_bwd_pass(
+    uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
 {
     extern __shared__ float2 smem[];
     float2* lds = smem;
@@ -547,31 +550,29 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     const int tile = sd->tile_base + (int)t;
     const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + sd->tab) + geo.zb
                                    : (const uint16_t*)(ws + sd->tabB) + (size_t)t * TILE;
-
-    RxC pre{}, post{};
-    if (ops.pre >= 0) pre = load_rx(cf, ops.pre, g);
-    if (ops.post >= 0) post = load_rx(cf, ops.post, g);
     const uint32_t gb = group_bits(geo.c);
-    const uint32_t m_pre = (ops.pre >= 0 && pre.flip) ? gb : 0u;
-    const uint32_t m_end = m_pre ^ ((ops.post >= 0 && post.flip) ? gb : 0u);
-    // conjugate phase table with the inverse factor of the preceding segment
-    if (ops.ph >= 0 && !ops.last) {
+    const RxC pre = load_rx(cf, ops.pre, g);
+    RxC post{};
+    if constexpr (KIND == B_MID) post = load_rx(cf, ops.post, g);
+    const uint32_t m_pre = pre.flip ? gb : 0u;
+    const uint32_t m_end = m_pre ^ ((KIND == B_MID && post.flip) ? gb : 0u);
+    if constexpr (KIND == B_MID) {
+        // conjugate phase table with the inverse factor of the preceding segment
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
-        const float2 F = pre.Fi;
         for (int i = tid; i < lut_len; i += THREADS) {
             const float2 e = L[i];
-            lut[i] = cmul(make_float2(e.x, -e.y), F);
+            lut[i] = cmul(make_float2(e.x, -e.y), pre.Fi);
         }
     }
     float2 ps[REGS], la[REGS];
     load_state<LS>(ps, sp, geo, tid);
-    if (!FUSED) load_state<LS>(la, sl, geo, tid);
+    if constexpr (KIND != B_FUSED) load_state<LS>(la, sl, geo, tid);
     __syncthreads();
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
     uint16_t cr[REGS];
-    if (FUSED) {
+    if constexpr (KIND == B_FUSED) {
         // psi_p = RX(pre) psi (slot q then holds amplitude q ^ m_pre)
-        seg_rot<CH, true>(ps, lds, geo.c, pre.t, tid);
+        seg_rot<CH, FULL, true>(ps, lds, geo.c, pre.t, tid);
         scale_regs(ps, pre.Ff);
         load_cut_L<LE>(cr, tab, tid, m_pre);
 #pragma unroll
@@ -581,73 +582,64 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
             la[r] = make_float2(c * ps[r].x, c * ps[r].y);
         }
         // the inverse rotation flips back: the stored lambda is unpermuted
-        seg_bwd<CH, false>(ps, la, lds, geo.c, pre, tid, acc_pre);
+        seg_bwd<CH, FULL, false>(ps, la, lds, geo.c, pre, tid, acc_pre);
         scale_regs(la, pre.Fi);
     } else {
-        seg_bwd<CH, true>(ps, la, lds, geo.c, pre, tid, acc_pre);
-        if (ops.ph >= 0) {
+        seg_bwd<CH, FULL, true>(ps, la, lds, geo.c, pre, tid, acc_pre);
+        if constexpr (KIND == B_SINGLE) {
+            scale_regs(ps, pre.Fi);
+            scale_regs(la, pre.Fi);
+        } else {
             load_cut_L<LE>(cr, tab, tid, m_pre);
             // on the rotated-but-unscaled states; rescale by |F|^2
             float a = 0.f;
 #pragma unroll
-            for (int r = 0; r < REGS; ++r)
-                a += (float)cr[r] * (la[r].x * ps[r].y - la[r].y * ps[r].x);
-            const float2 F = pre.Fi;
-            acc_ph = (double)a * (double)(F.x * F.x + F.y * F.y);
-            if (!ops.last) {
+            for (int r = 0; r < REGS; ++r) {
+                const float c = (float)cr[r];
+                a = fmaf(c * la[r].x, ps[r].y, a);
+                a = fmaf(-c * la[r].y, ps[r].x, a);
+            }
+            acc_ph = (double)a * (double)(pre.Fi.x * pre.Fi.x + pre.Fi.y * pre.Fi.y);
+            if constexpr (KIND == B_MID) {
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int r = 0; r < REGS; ++r) {
                     const float2 f = lut[cr[r]];
                     ps[r] = cmul(ps[r], f);
                     la[r] = cmul(la[r], f);
                 }
-            }
-        } else if (!ops.last) {
-            scale_regs(ps, pre.Fi);
-            scale_regs(la, pre.Fi);
-        }
-        if (ops.post >= 0) {
-            seg_bwd<CH, false>(ps, la, lds, geo.c, post, tid, acc_post);
-            if (!ops.last) {
+                __builtin_amdgcn_sched_barrier(0);
+                seg_bwd<CH, FULL, false>(ps, la, lds, geo.c, post, tid, acc_post);
                 scale_regs(ps, post.Fi);
                 scale_regs(la, post.Fi);
             }
         }
     }
     // partial sums (every thread takes part in each block_sum)
-    if (FUSED) {
+    if constexpr (KIND == B_FUSED) {
         const double e = block_sum(acc_e, red);
+        if (tid == 0) part.e[tile] = e;
+    }
+    {
         const double x = block_sum(acc_pre, red);
-        if (tid == 0) {
-            part.e[tile] = e;
-            part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = x;
-        }
-    } else {
-        {
-            const double x = block_sum(acc_pre, red);
-            if (tid == 0) part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = x;
-        }
-        if (ops.ph >= 0) {
-            const double x = block_sum(acc_ph, red);
-            if (tid == 0) part.gg[(size_t)ops.ph * T + tile] = x;
-        }
-        if (ops.post >= 0) {
-            const double x = block_sum(acc_post, red);
-            if (tid == 0) part.gb[((size_t)ops.post * MAX_GROUPS + g) * T + tile] = x;
-        }
+        if (tid == 0) part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = x;
     }
-    if (ops.last) return;
-    if (FUSED) {
+    if constexpr (KIND == B_MID || KIND == B_LAST) {
+        const double x = block_sum(acc_ph, red);
+        if (tid == 0) part.gg[(size_t)ops.ph * T + tile] = x;
+    }
+    if constexpr (KIND == B_MID) {
+        const double x = block_sum(acc_post, red);
+        if (tid == 0) part.gb[((size_t)ops.post * MAX_GROUPS + g) * T + tile] = x;
+    }
+    if constexpr (KIND == B_FUSED) {
         store_state<LS>(la, sl, geo, tid, 0u);
-        return;
-    }
-    // after pre (and post) the chain position is the end (or the start again)
-    if (ops.post >= 0) {
-        store_state<LS>(ps, sp, geo, tid, m_end);
-        store_state<LS>(la, sl, geo, tid, m_end);
-    } else {
+    } else if constexpr (KIND == B_SINGLE) {
         store_state<LE>(ps, sp, geo, tid, m_end);
         store_state<LE>(la, sl, geo, tid, m_end);
+    } else if constexpr (KIND == B_MID) {
+        store_state<LS>(ps, sp, geo, tid, m_end);
+        store_state<LS>(la, sl, geo, tid, m_end);
     }
 }
 
@@ -802,14 +794,30 @@ hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, con
 
 static size_t pass_lds(int lut_max) { return (size_t)(LDS_TILE + lut_max) * sizeof(float2); }
 
+// chain codes: 3 = group 0; 2 / 4 = a high group of 8 / 5..7 qubits;
+// 1 / 5 = a high group of 4 / 1..3 qubits (the second of each pair has
+// register bits that are not active qubits)
+#define PQ_LAUNCH_CH(KERNEL, KIND)                                                                              \
+    do {                                                                                                        \
+        switch (chain) {                                                                                        \
+        case 3: hipLaunchKernelGGL((KERNEL<3, true, KIND>), g, b, lds, s, ws, subs, work, ops, part); break;    \
+        case 2: hipLaunchKernelGGL((KERNEL<2, true, KIND>), g, b, lds, s, ws, subs, work, ops, part); break;    \
+        case 4: hipLaunchKernelGGL((KERNEL<2, false, KIND>), g, b, lds, s, ws, subs, work, ops, part); break;   \
+        case 1: hipLaunchKernelGGL((KERNEL<1, true, KIND>), g, b, lds, s, ws, subs, work, ops, part); break;    \
+        default: hipLaunchKernelGGL((KERNEL<1, false, KIND>), g, b, lds, s, ws, subs, work, ops, part); break;  \
+        }                                                                                                       \
+    } while (0)
+
 hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain, PassOps ops,
                            Partials part, int lut_max, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     const size_t lds = pass_lds(lut_max);
-    if (chain == 3) hipLaunchKernelGGL(k_fwd_pass<3>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
-    else if (chain == 2) hipLaunchKernelGGL(k_fwd_pass<2>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
-    else hipLaunchKernelGGL(k_fwd_pass<1>, dim3(nwork), dim3(THREADS), lds, s, ws, subs, work, ops, part);
+    const dim3 g(nwork), b(THREADS);
+    if (ops.init) PQ_LAUNCH_CH(k_fwd_pass, F_FIRST);
+    else if (ops.epi_e) PQ_LAUNCH_CH(k_fwd_pass, F_LAST);
+    else if (ops.ph >= 0) PQ_LAUNCH_CH(k_fwd_pass, F_MID);
+    else PQ_LAUNCH_CH(k_fwd_pass, F_SINGLE);
     return hipGetLastError();
 }
 
@@ -819,15 +827,10 @@ hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, i
     if (nwork <= 0) return hipSuccess;
     const size_t lds = pass_lds(lut_max);
     const dim3 g(nwork), b(THREADS);
-    if (ops.fused) {
-        if (chain == 3) hipLaunchKernelGGL((k_bwd_pass<3, true>), g, b, lds, s, ws, subs, work, ops, part);
-        else if (chain == 2) hipLaunchKernelGGL((k_bwd_pass<2, true>), g, b, lds, s, ws, subs, work, ops, part);
-        else hipLaunchKernelGGL((k_bwd_pass<1, true>), g, b, lds, s, ws, subs, work, ops, part);
-    } else {
-        if (chain == 3) hipLaunchKernelGGL((k_bwd_pass<3, false>), g, b, lds, s, ws, subs, work, ops, part);
-        else if (chain == 2) hipLaunchKernelGGL((k_bwd_pass<2, false>), g, b, lds, s, ws, subs, work, ops, part);
-        else hipLaunchKernelGGL((k_bwd_pass<1, false>), g, b, lds, s, ws, subs, work, ops, part);
-    }
+    if (ops.fused) PQ_LAUNCH_CH(k_bwd_pass, B_FUSED);
+    else if (ops.last) PQ_LAUNCH_CH(k_bwd_pass, B_LAST);
+    else if (ops.ph >= 0) PQ_LAUNCH_CH(k_bwd_pass, B_MID);
+    else PQ_LAUNCH_CH(k_bwd_pass, B_SINGLE);
     return hipGetLastError();
 }
 
