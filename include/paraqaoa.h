@@ -70,6 +70,23 @@ typedef void* qaoa_stream_t;
  * the k smallest candidate indices, probability 2^-n). Their states are not
  * stored (qaoa_state_offset reports QAOA_ERR_STATE for them). */
 #define QAOA_FLAG_SKIP_EDGELESS 0x4u
+/* Precision modes of the mixer (Sec. 2.2: U_M(beta) = prod_j e^{-i beta X_j}).
+ * For subgraphs with more than 12 qubits, the rotation of five of the qubits
+ * in the first qubit group (local qubits 0..3 and 9) runs as one dense
+ * 32 x 32 complex block on the matrix cores instead of the vector units:
+ *   MFMA_F32    FP32 matrix products (32x32x2);
+ *   MFMA_BF16X3 BF16 matrix products (32x32x16) on hi/lo splits of both
+ *               operands (x = hi + lo), keeping hi*hi + hi*lo + lo*hi;
+ *   MFMA_BF16X4 as BF16X3, with the block matrix split in three BF16 terms
+ *               (hi + mid + lo) and the products hi*hi + hi*lo + mid*hi +
+ *               lo*hi, which keeps the block unitary to FP32 rounding.
+ * Accumulation is FP32; all other steps are unchanged (FP32 amplitudes). At
+ * most one mode may be set (QAOA_ERR_INVALID_ARG otherwise); none can be
+ * combined with QAOA_FLAG_GRADIENT (QAOA_ERR_NOT_SUPPORTED). Subgraphs of at
+ * most 12 qubits keep the vector path. */
+#define QAOA_FLAG_MIXER_MFMA_F32 0x8u
+#define QAOA_FLAG_MIXER_MFMA_BF16X3 0x10u
+#define QAOA_FLAG_MIXER_MFMA_BF16X4 0x20u
 
 /* Workspace size for a batch (paper Sec. 3.3: the subgraphs {G[V_i]} that
  * Alg. 1 produces, each solved by its own QAOA instance).

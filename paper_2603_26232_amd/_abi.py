@@ -19,6 +19,9 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "paraqaoa.h")
 QAOA_FLAG_GRADIENT = 0x1
 QAOA_FLAG_TOPK_RAW = 0x2
 QAOA_FLAG_SKIP_EDGELESS = 0x4
+QAOA_FLAG_MIXER_MFMA_F32 = 0x8
+QAOA_FLAG_MIXER_MFMA_BF16X3 = 0x10
+QAOA_FLAG_MIXER_MFMA_BF16X4 = 0x20
 QAOA_MAX_QUBITS = 30
 QAOA_MAX_DEPTH = 32
 QAOA_MAX_K = 64

@@ -22,8 +22,11 @@ class QaoaBatch:
     """A batch of subgraphs on one GPU (states, cut tables, phase tables in
     one caller-owned workspace tensor)."""
 
+    MIXERS = {"valu": 0, "mfma_f32": _abi.QAOA_FLAG_MIXER_MFMA_F32, "mfma_bf16x3": _abi.QAOA_FLAG_MIXER_MFMA_BF16X3,
+              "mfma_bf16x4": _abi.QAOA_FLAG_MIXER_MFMA_BF16X4}
+
     def __init__(self, sizes, sub_edges, max_p, max_k=16, gradient=False, raw_topk=False,
-                 skip_edgeless=False, device="cuda", stream=None):
+                 skip_edgeless=False, device="cuda", stream=None, mixer="valu"):
         nq, off, u, v, w = batch_arrays(sizes, sub_edges)
         self.B = int(nq.shape[0])
         self.sizes = nq
@@ -31,7 +34,7 @@ class QaoaBatch:
         self.max_k = int(max_k)
         self.device = torch.device(device)
         flags = ((_abi.QAOA_FLAG_GRADIENT if gradient else 0) | (_abi.QAOA_FLAG_TOPK_RAW if raw_topk else 0)
-                 | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0))
+                 | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0) | self.MIXERS[mixer])
         self.flags = flags
         nbytes = _abi.qaoa_workspace_bytes(self.B, nq, off, w, self.max_p, self.max_k, flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

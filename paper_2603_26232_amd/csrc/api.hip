@@ -123,6 +123,7 @@ namespace {
 struct Plan {
     int32_t B = 0, max_p = 0, max_k = 0;
     uint32_t flags = 0;
+    int prec = 0;  // mixer block: 0 vector units, 1 FP32 MFMA, 2 / 3 BF16 split MFMA
     std::vector<SubDesc> subs;
     int32_t total_tiles = 0;
     int64_t total_edges = 0;
@@ -170,13 +171,20 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     if (!nq || !eoff) return fail(QAOA_ERR_INVALID_ARG, "num_qubits and edge_offsets are required");
     if (max_p < 1 || max_p > MAX_P) return fail(QAOA_ERR_OUT_OF_RANGE, "max_p = %d outside 1..%d", max_p, MAX_P);
     if (max_k < 1 || max_k > MAX_K) return fail(QAOA_ERR_OUT_OF_RANGE, "max_k = %d outside 1..%d", max_k, MAX_K);
-    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS))
+    const uint32_t mixer =
+        flags & (QAOA_FLAG_MIXER_MFMA_F32 | QAOA_FLAG_MIXER_MFMA_BF16X3 | QAOA_FLAG_MIXER_MFMA_BF16X4);
+    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS | mixer))
         return fail(QAOA_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if (mixer & (mixer - 1)) return fail(QAOA_ERR_INVALID_ARG, "at most one mixer precision mode may be set");
+    if (mixer && (flags & QAOA_FLAG_GRADIENT))
+        return fail(QAOA_ERR_NOT_SUPPORTED, "the matrix-core mixer modes have no gradient path");
     if (eoff[0] != 0) return fail(QAOA_ERR_INVALID_ARG, "edge_offsets[0] = %lld must be 0", (long long)eoff[0]);
     P.B = B;
     P.max_p = max_p;
     P.max_k = max_k;
     P.flags = flags;
+    P.prec = mixer == QAOA_FLAG_MIXER_MFMA_F32 ? 1 : mixer == QAOA_FLAG_MIXER_MFMA_BF16X3 ? 2
+           : mixer == QAOA_FLAG_MIXER_MFMA_BF16X4 ? 3 : 0;
     P.subs.assign(B, SubDesc{});
     const bool grad = flags & QAOA_FLAG_GRADIENT;
     int64_t tiles = 0;
@@ -532,7 +540,8 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
             o.init = i == 0;
             o.epi_e = i + 1 == passes.size();
             ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
-            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
+            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, P.prec,
+                                    st));
         }
     }
     h->state_valid = true;
@@ -564,8 +573,8 @@ extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, f
         if (!d.skip) tk += (double)(1ull << d.n) * 8.0;
     ProfScope ps("topk", st, tk + 16.0 * P.total_tiles * k);
     HIP_TRY(launch_topk(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_all), P.total_tiles, P.B, k,
-                        (P.flags & QAOA_FLAG_TOPK_RAW) ? 0 : 1, (uint64_t*)(h->ws + P.o_keys), nullptr, d_idx,
-                        d_prob, st));
+                        (P.flags & QAOA_FLAG_TOPK_RAW) ? 0 : 1, (uint64_t*)(h->ws + P.o_keys), d_idx, d_prob,
+                        st));
     return ok();
 }
 
@@ -598,7 +607,7 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
             PassOps o = fwd[i];
             o.init = i == 0;
             ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
-            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
+            HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, 0, st));
         }
         std::vector<Op> rev(ops.rbegin(), ops.rend());
         std::vector<PassOps> bwd = group_passes(rev);

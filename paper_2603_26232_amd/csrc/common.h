@@ -128,7 +128,7 @@ hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, con
 // chain: layout-chain code of the pass's group (3: group 0; 2 / 4: a high
 // group of 8 / 5..7 qubits; 1 / 5: a high group of 4 / 1..3 qubits)
 hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,
-                           PassOps ops, Partials part, int lut_max, hipStream_t s);
+                           PassOps ops, Partials part, int lut_max, int prec, hipStream_t s);
 hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,
                            PassOps ops, Partials part, int lut_max, hipStream_t s);
 hipError_t launch_small(uint8_t* ws, const SubDesc* subs, const int32_t* list, int nlist, int p,
@@ -137,8 +137,7 @@ hipError_t launch_reduce(const SubDesc* subs, int B, int p, int grad, Partials p
                          double* dgamma, double* dbeta, hipStream_t s);
 // ---- launchers (topk.hip) ----
 hipError_t launch_topk(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int B, int k,
-                       int canonical, uint64_t* keys_a, uint64_t* keys_b, uint32_t* idx,
-                       float* prob, hipStream_t s);
+                       int canonical, uint64_t* keys, uint32_t* idx, float* prob, hipStream_t s);
 // ---- launchers (cut.hip) ----
 hipError_t launch_maxcut_eval(int32_t nV, int64_t nE, const int32_t* u, const int32_t* v,
                               const int32_t* w, int64_t A, const uint32_t* assign, int64_t* cut,

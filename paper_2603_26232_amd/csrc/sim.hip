@@ -38,6 +38,9 @@
 #ifndef PQ_BWD_WAVES
 #define PQ_BWD_WAVES 2
 #endif
+#ifndef PQ_MF_WAVES
+#define PQ_MF_WAVES 3
+#endif
 
 namespace pq {
 
@@ -215,25 +218,153 @@ __device__ inline void round_coef(float (&tk)[4], float t, int c)
 // Tile bits of the group's qubits (the ones a flip permutes).
 __device__ inline uint32_t group_bits(int c) { return ((uint32_t)TILE - 1u) & ~((1u << c) - 1u); }
 
+// ---------------------------------------------------------------------------
+// Mixer block on the matrix cores (precision modes). In layout LL0 a wave
+// holds 32 blocks of 32 amplitudes: registers = tile bits 0..3, lane bit 5 =
+// tile bit 9, lane bits 0..4 = the block index (tile bits 4..8). The reduced
+// rotation of those five qubits, U = prod_j (I - i t X_j), is one dense 32 x 32
+// complex matrix with U[a'][a] = (-i t)^popcount(a' ^ a); as a real 64 x 64
+// matrix [[Re U, -Im U], [Im U, Re U]] it multiplies the 64 x 32 real block
+// matrix of the wave. The output rows are numbered so that the accumulator
+// layout of a 32 x 32 MFMA tile (lane L, register r holds row
+// 8 (r / 4) + 4 (L / 32) + r % 4 of column L % 32) is again layout LL0.
+// PREC 1: FP32 MFMA (32x32x2). PREC 2: BF16 MFMA (32x32x16) on hi/lo splits,
+// x = hi + lo, of both operands, keeping the hi*hi, hi*lo and lo*hi products.
+// PREC 3: as 2, but the block matrix is split in three BF16 terms (hi + mid +
+// lo, exact to FP32 rounding) and the products are hi*hi, hi*lo, mid*hi and
+// lo*hi: the rounding of the constant block then no longer makes it
+// measurably non-unitary (the two-term split changes the norm by ~1e-6 per
+// application, the same sign every time).
+// ---------------------------------------------------------------------------
+enum { PREC_VALU = 0, PREC_MFMA_F32 = 1, PREC_MFMA_BF16X3 = 2, PREC_MFMA_BF16X4 = 3 };
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline uint16_t bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo)
+{
+    const uint16_t h = bf16_bits(x);
+    hi = __builtin_bit_cast(__bf16, h);
+    lo = __builtin_bit_cast(__bf16, bf16_bits(x - bf16_value(h)));
+}
+
+template <int PREC>
+__device__ inline void mfma_block(float2 (&v)[REGS], float t, uint32_t tid)
+{
+    const uint32_t lane = tid & 63u;
+    const uint32_t i = lane & 31u, h = lane >> 5;
+    // output amplitude of A row i: a' = (4 (i / 8) + i % 4) | ((i / 4) % 2) << 4
+    const uint32_t arow = (4u * (i >> 3) + (i & 3u)) | (((i >> 2) & 1u) << 4);
+    const float t2 = t * t, t3 = t2 * t, t4 = t2 * t2, t5 = t4 * t;
+    // Re U and Im U of row arow, column a = s | h << 4, s = 0..15
+    float ure[16], uim[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int d = __popc(arow ^ ((uint32_t)s | (h << 4)));
+        // (-i t)^d = 1, -i t, -t^2, i t^3, t^4, -i t^5
+        const float w = d == 0 ? 1.f : d == 1 ? -t : d == 2 ? -t2 : d == 3 ? t3 : d == 4 ? t4 : -t5;
+        ure[s] = (d & 1) ? 0.f : w;
+        uim[s] = (d & 1) ? w : 0.f;
+    }
+    floatx16 re = {0.f}, im = {0.f};
+    if constexpr (PREC == PREC_MFMA_F32) {
+        // K row (2 s + h) of step s < 16 is Re psi(a), of step s + 16 Im psi(a)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            re = __builtin_amdgcn_mfma_f32_32x32x2f32(ure[s], v[s].x, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x2f32(uim[s], v[s].x, im, 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            re = __builtin_amdgcn_mfma_f32_32x32x2f32(-uim[s], v[s].y, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x2f32(ure[s], v[s].y, im, 0, 0, 0);
+        }
+    } else {
+        // step q (0..3): K rows 16 q + 8 h + e, e = 0..7, hold component q / 2
+        // of psi(a), a = 8 (q % 2) + e | h << 4
+        constexpr bool X4 = PREC == PREC_MFMA_BF16X4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = q >> 1, o = 8 * (q & 1);
+            bf16x8 bh, bl, rh, rm, rl, ih, im_, il;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                __bf16 x, y;
+                split_bf16(c ? v[o + e].y : v[o + e].x, x, y);
+                bh[e] = x;
+                bl[e] = y;
+                const float ar = c ? -uim[o + e] : ure[o + e];
+                const float ai = c ? ure[o + e] : uim[o + e];
+                split_bf16(ar, x, y);
+                rh[e] = x;
+                rm[e] = y;
+                if constexpr (X4) {
+                    const float rest = (ar - bf16_value(__builtin_bit_cast(uint16_t, x))) -
+                                       bf16_value(__builtin_bit_cast(uint16_t, y));
+                    rl[e] = __builtin_bit_cast(__bf16, bf16_bits(rest));
+                }
+                split_bf16(ai, x, y);
+                ih[e] = x;
+                im_[e] = y;
+                if constexpr (X4) {
+                    const float rest = (ai - bf16_value(__builtin_bit_cast(uint16_t, x))) -
+                                       bf16_value(__builtin_bit_cast(uint16_t, y));
+                    il[e] = __builtin_bit_cast(__bf16, bf16_bits(rest));
+                }
+            }
+            // smallest terms first
+            if constexpr (X4) re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rl, bh, re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rm, bh, re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bl, re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rh, bh, re, 0, 0, 0);
+            if constexpr (X4) im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(il, bh, im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(im_, bh, im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bl, im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ih, bh, im, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < REGS; ++r) v[r] = make_float2(re[r], im[r]);
+}
+
+// One rotation round in layout L. With a matrix-core mode, group 0 (CH 3)
+// rotates tile bits 0..3 and 9 by mfma_block in LL0 and leaves bit 9
+// (register bit 1 of LLIN) out of the LLIN round.
+template <int CH, int L, bool FULL, int PREC>
+__device__ inline void rot_round(float2 (&v)[REGS], int c, float t, uint32_t tid)
+{
+    if constexpr (PREC != PREC_VALU && CH == 3 && L == LL0) {
+        mfma_block<PREC>(v, t, tid);
+    } else {
+        float tk[4];
+        round_coef<L, FULL>(tk, t, c);
+        if constexpr (PREC != PREC_VALU && CH == 3 && L == LLIN) tk[1] = 0.f;
+        rx_round(v, tk);
+    }
+}
+
 // One RX segment (all qubits of the group, one layer) walking the layout
 // chain in direction DIR (true: start -> end), coefficient t.
-template <int CH, bool FULL, bool DIR>
+template <int CH, bool FULL, bool DIR, int PREC = PREC_VALU>
 __device__ inline void seg_rot(float2 (&v)[REGS], float2* lds, int c, float t, uint32_t tid)
 {
     constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
-    float tk[4];
-    round_coef<L0, FULL>(tk, t, c);
-    rx_round(v, tk);
+    rot_round<CH, L0, FULL, PREC>(v, c, t, tid);
     if constexpr (CH >= 2) {
         constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
         xchg<L0, L1>(lds, tid, v);
-        round_coef<L1, FULL>(tk, t, c);
-        rx_round(v, tk);
+        rot_round<CH, L1, FULL, PREC>(v, c, t, tid);
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, v);
-            round_coef<L2, FULL>(tk, t, c);
-            rx_round(v, tk);
+            rot_round<CH, L2, FULL, PREC>(v, c, t, tid);
         }
     }
 }
@@ -445,9 +576,9 @@ __global__ __launch_bounds__(THREADS) void k_angle_prep(uint8_t* ws, const SubDe
 // ---------------------------------------------------------------------------
 enum { F_FIRST = 0, F_SINGLE = 1, F_MID = 2, F_LAST = 3 };
 
-template <int CH, bool FULL, int KIND>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_WAVES))) void k_fwd_pass(
-    uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
+template <int CH, bool FULL, int KIND, int PREC>
+__device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops,
+                                              Partials part)
 {
     extern __shared__ float2 smem[];
     float2* lds = smem;
@@ -493,14 +624,14 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
     }
     __syncthreads();  // phase table staged
     if constexpr (HAS_PRE) {
-        seg_rot<CH, FULL, true>(v, lds, geo.c, pre.t, tid);
+        seg_rot<CH, FULL, true, PREC>(v, lds, geo.c, pre.t, tid);
         if constexpr (!HAS_PH) scale_regs(v, pre.Ff);
     }
     if constexpr (HAS_PH) {
 #pragma unroll
         for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
         // FIRST walks start -> end, MID walks back end -> start
-        seg_rot<CH, FULL, KIND == F_FIRST>(v, lds, geo.c, post.t, tid);
+        seg_rot<CH, FULL, KIND == F_FIRST, PREC>(v, lds, geo.c, post.t, tid);
         scale_regs(v, post.Ff);
     }
     if constexpr (KIND == F_LAST) {
@@ -514,6 +645,21 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_
     // after one segment the layout is the chain end; after two it is back at the start
     if constexpr (KIND == F_MID) store_state<LS>(v, st, geo, tid, m_end);
     else store_state<LE>(v, st, geo, tid, m_end);
+}
+
+template <int CH, bool FULL, int KIND>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_FWD_WAVES))) void k_fwd_pass(
+    uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
+{
+    fwd_pass_body<CH, FULL, KIND, PREC_VALU>(ws, subs, work, ops, part);
+}
+
+// group 0 with the mixer block on the matrix cores (more registers per lane)
+template <int KIND, int PREC>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_MF_WAVES))) void k_fwd_pass_mf(
+    uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
+{
+    fwd_pass_body<3, true, KIND, PREC>(ws, subs, work, ops, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -808,12 +954,32 @@ static size_t pass_lds(int lut_max) { return (size_t)(LDS_TILE + lut_max) * size
         }                                                                                                       \
     } while (0)
 
+// group 0 with a matrix-core mixer block (PREC 1 or 2)
+#define PQ_LAUNCH_MF(KIND)                                                                                      \
+    do {                                                                                                        \
+        if (prec == PREC_MFMA_F32)                                                                              \
+            hipLaunchKernelGGL((k_fwd_pass_mf<KIND, PREC_MFMA_F32>), g, b, lds, s, ws, subs, work, ops, part);  \
+        else if (prec == PREC_MFMA_BF16X3)                                                                      \
+            hipLaunchKernelGGL((k_fwd_pass_mf<KIND, PREC_MFMA_BF16X3>), g, b, lds, s, ws, subs, work, ops,      \
+                               part);                                                                           \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_fwd_pass_mf<KIND, PREC_MFMA_BF16X4>), g, b, lds, s, ws, subs, work, ops,      \
+                               part);                                                                           \
+    } while (0)
+
 hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain, PassOps ops,
-                           Partials part, int lut_max, hipStream_t s)
+                           Partials part, int lut_max, int prec, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     const size_t lds = pass_lds(lut_max);
     const dim3 g(nwork), b(THREADS);
+    if (prec != PREC_VALU && chain == 3) {
+        if (ops.init) PQ_LAUNCH_MF(F_FIRST);
+        else if (ops.epi_e) PQ_LAUNCH_MF(F_LAST);
+        else if (ops.ph >= 0) PQ_LAUNCH_MF(F_MID);
+        else PQ_LAUNCH_MF(F_SINGLE);
+        return hipGetLastError();
+    }
     if (ops.init) PQ_LAUNCH_CH(k_fwd_pass, F_FIRST);
     else if (ops.epi_e) PQ_LAUNCH_CH(k_fwd_pass, F_LAST);
     else if (ops.ph >= 0) PQ_LAUNCH_CH(k_fwd_pass, F_MID);

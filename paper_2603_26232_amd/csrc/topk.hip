@@ -4,34 +4,90 @@
 //
 // Each candidate becomes one unique 64-bit key, (bits of pi as float) << 32 |
 // (0xFFFFFFFF - z): pi >= 0, so the float bit pattern orders like the value,
-// and a larger low word means a smaller z. Stage 1 sorts the candidates of
-// one 4096-amplitude tile in LDS (bitonic) and keeps the best k; stage 2
-// folds the per-tile lists of a subgraph 2048 keys at a time into a running
-// best-k. Canonical mode takes only z with bit 0 clear (pi(z) = pi(~z)).
+// and a larger low word means a smaller z. Every valid key is nonzero (z <
+// 2^30), so 0 serves as padding below all of them.
+//
+// Both stages find the k largest keys of a set by a most-significant-digit
+// radix select in LDS (8-bit digits, one histogram per digit, stopping as
+// soon as every key that shares the current prefix is needed), instead of
+// sorting: stage 1 takes one 4096-amplitude tile per block, with its
+// candidates in registers, and writes the tile's best k unsorted; stage 2
+// selects a subgraph's best k from its per-tile lists and sorts only those.
+// Canonical mode takes only z with bit 0 clear (pi(z) = pi(~z)).
 #include "common.h"
 
 namespace pq {
 
-constexpr int SORT_N = 4096;
+struct SelState {
+    int hist[256];
+    int wsum[16];
+    int digit, qrem, done, count;
+    uint64_t out[MAX_K];
+};
 
-// descending bitonic sort of s[0..n) (n a power of two, n <= SORT_N)
-__device__ void bitonic_desc(uint64_t* s, int n)
+// the digit (from the top) that holds the q-th largest counted key; sets
+// done when exactly q keys were counted (then all of them are taken)
+__device__ void pick_digit(SelState& S, int q)
 {
-    for (int size = 2; size <= n; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
-                const int lo = 2 * stride * (i / stride) + (i % stride);
-                const int hi = lo + stride;
-                const uint64_t a = s[lo], b = s[hi];
-                const bool desc = (lo & size) == 0;
-                if (desc ? (a < b) : (a > b)) {
-                    s[lo] = b;
-                    s[hi] = a;
-                }
-            }
-            __syncthreads();
+    const int t = threadIdx.x;
+    int h = 0, incl = 0;
+    if (t < 256) {
+        h = S.hist[255 - t];
+        incl = h;
+        const int lane = t & 63;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) S.wsum[t >> 6] = incl;
+    }
+    __syncthreads();
+    if (t < 256) {
+        int base = 0;
+        for (int w = 0; w < (t >> 6); ++w) base += S.wsum[w];
+        incl += base;
+        const int excl = incl - h;
+        if (t == 255) S.done = (incl == q);
+        if (h > 0 && excl < q && q <= incl) {
+            S.digit = 255 - t;
+            S.qrem = q - excl;
         }
     }
+    __syncthreads();
+}
+
+// Radix select of the q largest keys produced by src(i), i < n_local per
+// thread. Returns (prefix, digits) such that a key is among the q largest iff
+// digits == 0 or key >> (64 - 8 digits) >= prefix. With unique keys this
+// selects exactly q; with repeated keys (padding) it may select more.
+template <typename Src>
+__device__ void radix_select(SelState& S, const Src& src, int n_local, int q, uint64_t& prefix, int& digits)
+{
+    const int t = threadIdx.x;
+    prefix = 0;
+    digits = 0;
+    for (int r = 0; r < 8; ++r) {
+        if (t < 256) S.hist[t] = 0;
+        __syncthreads();
+        const int shift = 56 - 8 * r;
+        for (int i = 0; i < n_local; ++i) {
+            const uint64_t key = src(i);
+            if (r == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&S.hist[(int)((key >> shift) & 255)], 1);
+        }
+        __syncthreads();
+        pick_digit(S, q);
+        if (S.done) return;
+        prefix = (prefix << 8) | (uint64_t)S.digit;
+        q = S.qrem;
+        digits = r + 1;
+        __syncthreads();  // everyone has read digit/qrem before the next round
+    }
+}
+
+__device__ inline bool selected(uint64_t key, uint64_t prefix, int digits)
+{
+    return digits == 0 || (key >> (64 - 8 * digits)) >= prefix;
 }
 
 __device__ inline uint64_t make_key(float2 a, uint32_t z)
@@ -40,69 +96,108 @@ __device__ inline uint64_t make_key(float2 a, uint32_t z)
     return ((uint64_t)__float_as_uint(pr) << 32) | (uint64_t)(0xFFFFFFFFu - z);
 }
 
-// stage 1: one tile of one subgraph -> best k keys of that tile
+// stage 1: one tile of one subgraph -> its best k keys (unsorted, 0-padded)
+template <bool CANON>
 __global__ __launch_bounds__(THREADS) void k_topk_tile(const uint8_t* ws, const SubDesc* subs, const int2* work,
-                                                      int k, int canonical, uint64_t* out)
+                                                      int k, uint64_t* out)
 {
-    __shared__ uint64_t s[SORT_N];
+    constexpr int PER = CANON ? 8 : 16;  // candidates per thread (4096 / 256 / step)
+    __shared__ SelState S;
     const int2 wk = work[blockIdx.x];
-    const SubDesc d = subs[wk.x];
-    const uint32_t t = (uint32_t)wk.y;
-    const float2* st = (const float2*)(ws + d.psi);
-    const uint32_t dim = 1u << d.n;
-    const uint32_t span = dim < (uint32_t)TILE ? dim : (uint32_t)TILE;
-    const uint32_t step = canonical ? 2u : 1u;
-    const uint32_t cnt = span / step;  // candidates in this tile
-    int n2 = 1;
-    while (n2 < (int)cnt) n2 <<= 1;
-    for (int i = threadIdx.x; i < n2; i += THREADS) {
-        uint64_t key = 0;
-        if ((uint32_t)i < cnt) {
-            const uint32_t z = t * TILE + (uint32_t)i * step;
-            key = make_key(st[z], z);
+    const SubDesc* d = subs + wk.x;
+    const int n = d->n;
+    const uint32_t base = (uint32_t)wk.y * TILE;
+    const float4* st = (const float4*)(ws + d->psi) + base / 2;
+    const uint32_t span = n < TILE_BITS ? (1u << n) : (uint32_t)TILE;
+    const uint32_t npair = span / 2;  // float4 = amplitudes (2c, 2c + 1)
+    const int t = threadIdx.x;
+    uint64_t key[PER];
+#pragma unroll
+    for (int j = 0; j < (CANON ? PER : PER / 2); ++j) {
+        const uint32_t c = (uint32_t)t + (uint32_t)j * THREADS;
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+        const bool ok = c < npair;
+        if (ok) a = st[c];
+        if (CANON) {
+            key[j] = ok ? make_key(make_float2(a.x, a.y), base + 2 * c) : 0ull;
+        } else {
+            key[2 * j] = ok ? make_key(make_float2(a.x, a.y), base + 2 * c) : 0ull;
+            key[2 * j + 1] = ok ? make_key(make_float2(a.z, a.w), base + 2 * c + 1) : 0ull;
         }
-        s[i] = key;
+    }
+    const int cnt = (int)(CANON ? npair : span);
+    const int q = k < cnt ? k : cnt;
+    uint64_t prefix;
+    int digits;
+    if (t == 0) S.count = 0;
+    radix_select(S, [&](int i) { return key[i]; }, PER, q, prefix, digits);
+    uint64_t* o = out + ((size_t)d->tile_base + wk.y) * k;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        if (key[i] != 0ull && selected(key[i], prefix, digits)) {
+            const int slot = atomicAdd(&S.count, 1);
+            if (slot < k) o[slot] = key[i];
+        }
     }
     __syncthreads();
-    bitonic_desc(s, n2);
-    uint64_t* o = out + ((size_t)d.tile_base + t) * k;
-    for (int i = threadIdx.x; i < k; i += THREADS) o[i] = (i < n2) ? s[i] : 0ull;
+    for (int i = S.count + t; i < k; i += THREADS) o[i] = 0ull;
 }
 
-// stage 2: fold the ntiles*k keys of a subgraph into its best k; write results
-__global__ __launch_bounds__(THREADS) void k_topk_merge(const SubDesc* subs, int k, int canonical, const uint64_t* in,
-                                                       uint32_t* idx, float* prob)
+// stage 2: a subgraph's ntiles * k keys -> its best k, sorted; results
+constexpr int MERGE_THREADS = 1024;
+
+__global__ __launch_bounds__(MERGE_THREADS) void k_topk_merge(const SubDesc* subs, int k, int canonical,
+                                                             const uint64_t* in, uint32_t* idx, float* prob)
 {
-    __shared__ uint64_t s[SORT_N];
+    __shared__ SelState S;
     const int b = blockIdx.x;
-    const SubDesc d = subs[b];
-    if (d.skip) {
+    const SubDesc* d = subs + b;
+    const int t = threadIdx.x;
+    if (d->skip) {
         // edgeless subgraph: |psi|^2 = 2^-n everywhere, ties broken by index
         const uint32_t step = canonical ? 2u : 1u;
-        const uint64_t cnt = (1ull << d.n) / step;
-        for (int i = threadIdx.x; i < k; i += THREADS) {
+        const uint64_t cnt = (1ull << d->n) / step;
+        for (int i = t; i < k; i += MERGE_THREADS) {
             const bool ok = (uint64_t)i < cnt;
             idx[(size_t)b * k + i] = ok ? (uint32_t)i * step : 0xFFFFFFFFu;
-            prob[(size_t)b * k + i] = ok ? ldexpf(1.0f, -d.n) : -1.0f;
+            prob[(size_t)b * k + i] = ok ? ldexpf(1.0f, -d->n) : -1.0f;
         }
         return;
     }
-    const size_t total = (size_t)d.ntiles * k;
-    const uint64_t* src = in + (size_t)d.tile_base * k;
-    const int chunk = SORT_N / 2;
-    for (int i = threadIdx.x; i < SORT_N; i += THREADS) s[i] = 0ull;
-    __syncthreads();
-    for (size_t off = 0; off < total; off += chunk) {
-        // slots [0, k) hold the running best; [k, k + chunk) the next keys
-        for (int i = threadIdx.x; i < SORT_N - k; i += THREADS) {
-            const size_t j = off + (size_t)i;
-            s[k + i] = (i < chunk && j < total) ? src[j] : 0ull;
+    const int total = d->ntiles * k;
+    const uint64_t* src = in + (size_t)d->tile_base * k;
+    const int nloc = (total - t + MERGE_THREADS - 1) / MERGE_THREADS;  // keys t, t + 1024, ...
+    uint64_t prefix;
+    int digits;
+    if (t == 0) S.count = 0;
+    if (t < MAX_K) S.out[t] = 0ull;
+    radix_select(S, [&](int i) { return src[t + (size_t)i * MERGE_THREADS]; }, nloc, k, prefix, digits);
+    for (int i = 0; i < nloc; ++i) {
+        const uint64_t key = src[t + (size_t)i * MERGE_THREADS];
+        if (key != 0ull && selected(key, prefix, digits)) {
+            const int slot = atomicAdd(&S.count, 1);
+            if (slot < k) S.out[slot] = key;
         }
-        __syncthreads();
-        bitonic_desc(s, SORT_N);
     }
-    for (int i = threadIdx.x; i < k; i += THREADS) {
-        const uint64_t key = s[i];
+    __syncthreads();
+    // sort the (at most 64) winners descending: bitonic over 64 slots
+    for (int size = 2; size <= MAX_K; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (t < MAX_K / 2) {
+                const int lo = 2 * stride * (t / stride) + (t % stride);
+                const int hi = lo + stride;
+                const uint64_t a = S.out[lo], c = S.out[hi];
+                const bool desc = (lo & size) == 0;
+                if (desc ? (a < c) : (a > c)) {
+                    S.out[lo] = c;
+                    S.out[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < k; i += MERGE_THREADS) {
+        const uint64_t key = S.out[i];
         if (key == 0ull) {
             idx[(size_t)b * k + i] = 0xFFFFFFFFu;
             prob[(size_t)b * k + i] = -1.0f;
@@ -114,16 +209,17 @@ __global__ __launch_bounds__(THREADS) void k_topk_merge(const SubDesc* subs, int
 }
 
 hipError_t launch_topk(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int B, int k,
-                       int canonical, uint64_t* keys_a, uint64_t* keys_b, uint32_t* idx, float* prob,
-                       hipStream_t s)
+                       int canonical, uint64_t* keys, uint32_t* idx, float* prob, hipStream_t s)
 {
-    (void)keys_b;
     if (nwork > 0) {
-        hipLaunchKernelGGL(k_topk_tile, dim3(nwork), dim3(THREADS), 0, s, ws, subs, work, k, canonical, keys_a);
+        if (canonical)
+            hipLaunchKernelGGL(k_topk_tile<true>, dim3(nwork), dim3(THREADS), 0, s, ws, subs, work, k, keys);
+        else
+            hipLaunchKernelGGL(k_topk_tile<false>, dim3(nwork), dim3(THREADS), 0, s, ws, subs, work, k, keys);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_topk_merge, dim3(B), dim3(THREADS), 0, s, subs, k, canonical, keys_a, idx, prob);
+    hipLaunchKernelGGL(k_topk_merge, dim3(B), dim3(MERGE_THREADS), 0, s, subs, k, canonical, keys, idx, prob);
     return hipGetLastError();
 }
 

@@ -132,3 +132,19 @@ def test_generators_shapes():
     # counter-based stream: any window equals the same slice of a longer draw
     a = synth.splitmix64(9, 0, 100)
     assert np.array_equal(a[40:60], synth.splitmix64(9, 40, 20))
+
+
+def test_mixer_precision_flags():
+    e = (np.array([0], np.int32), np.array([1], np.int32), np.array([1], np.int32))
+    base = _ws([16], [e])
+    for f in (_abi.QAOA_FLAG_MIXER_MFMA_F32, _abi.QAOA_FLAG_MIXER_MFMA_BF16X3, _abi.QAOA_FLAG_MIXER_MFMA_BF16X4):
+        assert _ws([16], [e], flags=f) == base  # same layout, no extra memory
+        with pytest.raises(_abi.QaoaError) as ei:
+            _ws([16], [e], flags=f | _abi.QAOA_FLAG_GRADIENT)
+        assert ei.value.status == 6
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([16], [e], flags=_abi.QAOA_FLAG_MIXER_MFMA_F32 | _abi.QAOA_FLAG_MIXER_MFMA_BF16X3)
+    assert ei.value.status == 1
+    with pytest.raises(_abi.QaoaError) as ei:
+        _ws([16], [e], flags=_abi.QAOA_FLAG_MIXER_MFMA_BF16X3 | _abi.QAOA_FLAG_MIXER_MFMA_BF16X4)
+    assert ei.value.status == 1
