@@ -461,6 +461,35 @@ __device__ inline double block_sum(double x, double* red)
     return s;
 }
 
+// three deterministic block sums with one barrier pair
+__device__ inline void block_sum3(double& a, double& b, double& c, double* red)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    const uint32_t tid = threadIdx.x;
+    const int nw = (int)(blockDim.x >> 6);
+    if ((tid & 63u) == 0) {
+        red[tid >> 6] = a;
+        red[nw + (tid >> 6)] = b;
+        red[2 * nw + (tid >> 6)] = c;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double x = 0.0, y = 0.0, z = 0.0;
+        for (int i = 0; i < nw; ++i) {
+            x += red[i];
+            y += red[nw + i];
+            z += red[2 * nw + i];
+        }
+        a = x;
+        b = y;
+        c = z;
+    }
+}
+
 __device__ inline uint32_t cut_of(uint32_t z, const int32_t* E, int ne)
 {
     uint32_t c = 0;
@@ -634,17 +663,20 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
         seg_rot<CH, FULL, KIND == F_FIRST, PREC>(v, lds, geo.c, post.t, tid);
         scale_regs(v, post.Ff);
     }
+    double acc = 0.0;
     if constexpr (KIND == F_LAST) {
-        double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < REGS; ++r)
             acc += ((double)v[r].x * v[r].x + (double)v[r].y * v[r].y) * (double)cr[r];
+    }
+    // after one segment the layout is the chain end; after two it is back at
+    // the start (stores first: they drain while the partial sum is reduced)
+    if constexpr (KIND == F_MID) store_state<LS>(v, st, geo, tid, m_end);
+    else store_state<LE>(v, st, geo, tid, m_end);
+    if constexpr (KIND == F_LAST) {
         acc = block_sum(acc, red);
         if (tid == 0) part.e[sd->tile_base + t] = acc;
     }
-    // after one segment the layout is the chain end; after two it is back at the start
-    if constexpr (KIND == F_MID) store_state<LS>(v, st, geo, tid, m_end);
-    else store_state<LE>(v, st, geo, tid, m_end);
 }
 
 template <int CH, bool FULL, int KIND>
@@ -680,7 +712,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     extern __shared__ float2 smem[];
     float2* lds = smem;
     float2* lut = smem + LDS_TILE;
-    __shared__ double red[THREADS / 64];
+    __shared__ double red[3 * THREADS / 64];
     constexpr int LS = ChainAt<CH, 0>::L, LE = ChainAt<CH, CH - 1>::L;
     const uint32_t tid = threadIdx.x;
     const int2 wk = work[blockIdx.x];
@@ -761,23 +793,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
             }
         }
     }
-    // partial sums (every thread takes part in each block_sum)
-    if constexpr (KIND == B_FUSED) {
-        const double e = block_sum(acc_e, red);
-        if (tid == 0) part.e[tile] = e;
-    }
-    {
-        const double x = block_sum(acc_pre, red);
-        if (tid == 0) part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = x;
-    }
-    if constexpr (KIND == B_MID || KIND == B_LAST) {
-        const double x = block_sum(acc_ph, red);
-        if (tid == 0) part.gg[(size_t)ops.ph * T + tile] = x;
-    }
-    if constexpr (KIND == B_MID) {
-        const double x = block_sum(acc_post, red);
-        if (tid == 0) part.gb[((size_t)ops.post * MAX_GROUPS + g) * T + tile] = x;
-    }
+    // results first (the stores drain while the partial sums are reduced)
     if constexpr (KIND == B_FUSED) {
         store_state<LS>(la, sl, geo, tid, 0u);
     } else if constexpr (KIND == B_SINGLE) {
@@ -786,6 +802,15 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     } else if constexpr (KIND == B_MID) {
         store_state<LS>(ps, sp, geo, tid, m_end);
         store_state<LS>(la, sl, geo, tid, m_end);
+    }
+    // partial sums: (<C> or gamma, beta of pre, beta of post)
+    double s0 = KIND == B_FUSED ? acc_e : acc_ph, s1 = acc_pre, s2 = acc_post;
+    block_sum3(s0, s1, s2, red);
+    if (tid == 0) {
+        if constexpr (KIND == B_FUSED) part.e[tile] = s0;
+        if constexpr (KIND == B_MID || KIND == B_LAST) part.gg[(size_t)ops.ph * T + tile] = s0;
+        part.gb[((size_t)ops.pre * MAX_GROUPS + g) * T + tile] = s1;
+        if constexpr (KIND == B_MID) part.gb[((size_t)ops.post * MAX_GROUPS + g) * T + tile] = s2;
     }
 }
 
