@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the ParaQAOA hot path on one MI355X.
 
-One step = one whole plain-method solve of the 400-vertex workload: batch
-build with integer cut tables, 50 Adam steps of every subgraph's angles on
-exact adjoint gradients, the final state and <C>, top-16 extraction, the
-level-wise beam merge (W = 4096) and the integer CutVal of the winner.
-Workload: Erdos-Renyi G(400, 0.05), seed 0, unit weights, partitioned into
-21 chained subgraphs of 20 vertices (20 qubits, 2^20 complex64 amplitudes
-each), QAOA depth p = 3.
+Default workload (plain400): one step = one whole plain-method solve of the
+400-vertex graph: batch build with integer cut tables, 50 Adam steps of every
+subgraph's angles on exact adjoint gradients, the final state and <C>, top-16
+extraction, the level-wise beam merge (W = 4096) and the integer CutVal of the
+winner. Erdos-Renyi G(400, 0.05), seed 0, unit weights, partitioned into 21
+chained subgraphs of 20 vertices (20 qubits, 2^20 complex64 amplitudes each),
+QAOA depth p = 3.
+
+Other workloads (--workload):
+  ragged2000   the same solve on G(2000, 0.01), seed 0, a chain of ragged
+               subgraphs of 14..26 vertices (sizes from stream seed 1), edgeless
+               subgraphs skipped (closed form); reports the 2k-vertex solve time.
+  precision26  one forward evaluation (all layers + <C>) of 32 random 3-regular
+               graphs on 26 vertices, p = 4, angles U(0, pi); --mixer picks the
+               mixer precision mode.
 
 value = amplitude updates per second: per forward evaluation every layer
 applies n RX gates and one diagonal phase to each amplitude, U = sum_b
-p (n_b + 1) 2^n_b; an optimiser step is a forward evaluation plus the
-adjoint sweep over two states (3 U), and the final evaluation adds U.
+p (n_b + 1) 2^n_b over simulated subgraphs; an optimiser step is a forward
+evaluation plus the adjoint sweep over two states (3 U), and the final
+evaluation adds U.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -36,10 +45,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_record(kernel):
+def traffic_record(kernel, workload):
     """Measured HBM traffic per launch of `kernel` from the committed PMC
     summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_plain400.txt")
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
     rec = None
@@ -55,16 +64,132 @@ def traffic_record(kernel):
     return rec
 
 
+def amp_updates(sizes, p):
+    return sum(p * (int(n) + 1) * (1 << int(n)) for n in sizes)
+
+
+def workload_solve(args, name):
+    """plain400 / ragged2000: the plain-method solve as one step."""
+    import numpy as np
+    from paper_2603_26232_amd import synth
+    from paper_2603_26232_amd.partition import partition_equal, partition_chain
+    from paper_2603_26232_amd.solve import Solver, SolveConfig, cold_start
+
+    if name == "plain400":
+        g = synth.erdos_renyi(400, 0.05, 0)
+        part = partition_equal(400, 20)
+        skip = False
+        desc = "plain-method solve, G(400,0.05) seed 0, 21 subgraphs x 20 qubits, p=3, 50 Adam steps, top-16, " \
+               "beam 4096, CutVal"
+    else:
+        g = synth.erdos_renyi(2000, 0.01, 0)
+        part = partition_chain(2000, synth.ragged_sizes(1, 14, 26, 2000))
+        skip = True
+        desc = "plain-method solve, G(2000,0.01) seed 0, ragged chain of 14..26-qubit subgraphs, edgeless " \
+               "skipped, p=3, 50 Adam steps, top-16, beam 4096, CutVal"
+    cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
+    log(f"bench: graph {g}, {part.M} subgraphs of sizes {min(part.size)}..{max(part.size)}, p={cfg.p}, "
+        f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
+    S = Solver(g, part, cfg, skip_edgeless=skip)
+    nE = np.array([len(e[0]) for e in S.sub_edges])
+    sim = [int(n) for n, e in zip(part.size, nE) if not (skip and e == 0)]
+    U = amp_updates(sim, cfg.p)
+
+    def step():
+        S.rebuild()
+        S.run(graph=args.graph)
+
+    def summary():
+        r = S.result()
+        return {"solve": {"cut": r.cut, "sum_E": float(np.sum(r.energies))}}
+
+    def cpu_baseline():
+        import oracle
+        # bounded sample: every subgraph (plain400) or every 2nd simulated
+        # subgraph of at most 22 qubits (ragged2000), T Adam steps with the
+        # final evaluation
+        idx = list(range(part.M)) if name == "plain400" else \
+            [b for b in range(part.M) if not (skip and nE[b] == 0) and part.size[b] <= 22][::2]
+        which = "all" if name == "plain400" else "every 2nd simulated one of at most 22 qubits"
+        T = args.cpu_iters
+        sizes = [int(part.size[b]) for b in idx]
+        edges = [S.sub_edges[b] for b in idx]
+        g0, b0 = cold_start(cfg.p, len(idx))
+        log(f"bench: CPU baseline: FP64 oracle, {len(idx)} subgraphs x ({T} Adam steps + final evaluation)")
+        c0 = time.perf_counter()
+        oracle.solve_batch(sizes, edges, g0, b0, T, cfg.k, lr=cfg.lr)
+        c1 = time.perf_counter()
+        val = (3 * T + 1) * amp_updates(sizes, cfg.p) / (c1 - c0)
+        return {"value": val, "unit": "amp-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "seconds": round(c1 - c0, 2),
+                "sample": f"{len(idx)} subgraphs ({which}) of this workload, {T} Adam steps with adjoint "
+                          f"gradients + final evaluation and top-{cfg.k} (FP64)"}
+
+    config = {"workload": desc, "graph_replay": bool(args.graph), "vertices": g.num_vertices, "edges": g.num_edges,
+              "subgraphs": part.M, "simulated_subgraphs": len(sim),
+              "qubits": [int(min(part.size)), int(max(part.size))],
+              "p": cfg.p, "adam_steps": cfg.iters, "k": cfg.k, "beam": cfg.beam}
+    return dict(step=step, updates=(3 * cfg.iters + 1) * U, config=config, summary=summary,
+                cpu_baseline=cpu_baseline, close=S.close, dtype="fp32")
+
+
+def workload_precision(args):
+    """precision26: one forward evaluation per step."""
+    import numpy as np
+    import torch
+    from paper_2603_26232_amd import synth
+    from paper_2603_26232_amd.batch import QaoaBatch
+
+    graphs = [synth.random_regular3(26, s) for s in range(32)]
+    edges = [(gr.u, gr.v, gr.w) for gr in graphs]
+    ang = [synth.uniform_angles(2000 + s, 4) for s in range(32)]
+    gamma = np.concatenate([a[0] for a in ang])
+    beta = np.concatenate([a[1] for a in ang])
+    bt = QaoaBatch([26] * 32, edges, max_p=4, max_k=8, mixer=args.mixer)
+    g = torch.as_tensor(gamma, device="cuda")
+    b = torch.as_tensor(beta, device="cuda")
+    E = torch.empty(32, dtype=torch.float64, device="cuda")
+    U = amp_updates([26] * 32, 4)
+
+    def step():
+        bt.apply_layers(g, b)
+        bt.expectation(E)
+
+    def summary():
+        return {"sum_E": float(E.sum())}
+
+    def cpu_baseline():
+        import oracle
+        sizes, sub = [26] * 2, edges[:2]
+        log("bench: CPU baseline: FP64 oracle, 2 of the 32 subgraphs, one forward evaluation each")
+        c0 = time.perf_counter()
+        oracle.eval_batch(sizes, sub, gamma[:2], beta[:2])
+        c1 = time.perf_counter()
+        return {"value": amp_updates(sizes, 4) / (c1 - c0), "unit": "amp-updates/s",
+                "cores": oracle.num_threads(), "kind": "oracle", "seconds": round(c1 - c0, 2),
+                "sample": "2 of the 32 subgraphs (26 qubits, p = 4), one FP64 forward evaluation with <C>"}
+
+    dtype = {"valu": "fp32", "mfma_f32": "fp32", "mfma_bf16x3": "bf16x3 (mixer block)",
+             "mfma_bf16x4": "bf16x4 (mixer block)"}[args.mixer]
+    config = {"workload": "forward evaluation, 32 random 3-regular graphs x 26 qubits, p=4, angles U(0,pi)",
+              "mixer": args.mixer, "subgraphs": 32, "qubits": 26, "p": 4}
+    return dict(step=step, updates=U, config=config, summary=summary, cpu_baseline=cpu_baseline,
+                close=bt.close, dtype=dtype)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["plain400", "ragged2000", "precision26"], default="plain400")
+    ap.add_argument("--mixer", choices=["valu", "mfma_f32", "mfma_bf16x3", "mfma_bf16x4"], default="valu",
+                    help="mixer precision mode (precision26 only)")
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the Adam step from a captured HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration, copy bandwidth)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the hot path "
@@ -72,42 +197,59 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2603_26232_amd import synth, _abi
-    from paper_2603_26232_amd.partition import partition_equal
-    from paper_2603_26232_amd.solve import Solver, SolveConfig, cold_start
+    from paper_2603_26232_amd import _abi
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     if args.copy_probe:
+        # one untimed copy, then three timed ones: four copies in all
         n = 1 << 30
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
         for _ in range(3):
             dst.copy_(src)
+        ev[1].record()
         torch.cuda.synchronize()
-        log(f"bench: copy probe: 3 copies of {n} bytes (read {n}, write {n} per copy)")
+        ms = ev[0].elapsed_time(ev[1]) / 3
+        log(f"bench: copy probe: {n} bytes read + {n} written per copy, {ms:.3f} ms per copy, "
+            f"{2 * n / (ms * 1e-3) / 1e9:.1f} GB/s")
         return
-    g = synth.erdos_renyi(400, 0.05, 0)
-    part = partition_equal(400, 20)
-    cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
-    log(f"bench: graph {g}, {part.M} subgraphs of sizes {sorted(set(part.size.tolist()))}, p={cfg.p}, "
-        f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
-    S = Solver(g, part, cfg)
-    U = sum(cfg.p * (int(n) + 1) * (1 << int(n)) for n in part.size)
-    updates_per_step = (3 * cfg.iters + 1) * U
 
-    def step():
-        S.rebuild()
-        S.run(graph=args.graph)
+    W = workload_precision(args) if args.workload == "precision26" else workload_solve(args, args.workload)
+    step = W["step"]
 
+    def read_profile():
+        kern = {}
+        for k in KERNELS:
+            n, ms, by = _abi.qaoa_profile_read(k)
+            if n:
+                kern[k] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n, "algo_bytes": by}
+        return kern
+
+    # warm-up; the last warm-up step is timed kernel by kernel (every launch
+    # bracketed by events) to find the kernel with the largest share
+    kern = {}
     for i in range(args.warmup):
+        if i == args.warmup - 1:
+            _abi.qaoa_profile_select(None)
+            _abi.qaoa_profile_enable(1)
         step()
     torch.cuda.synchronize()
+    if args.warmup:
+        kern = read_profile()
+        _abi.qaoa_profile_enable(0)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else (
+        "fwd_pass" if args.workload == "precision26" else "bwd_pass")
     if args.graph:
         log("bench: Adam steps replay a captured HIP graph")
-    log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps")
+    log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps (kernel events on {dom} only)")
+    # timed region: events only around the dominant kernel's launches
+    _abi.qaoa_profile_select(dom)
     _abi.qaoa_profile_enable(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -115,26 +257,22 @@ def main():
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {}
-    for k in KERNELS:
-        n, ms, by = _abi.qaoa_profile_read(k)
-        if n:
-            kern[k] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n, "algo_bytes": by}
+    timed = read_profile()
     _abi.qaoa_profile_enable(0)
-    res = S.result()
+    _abi.qaoa_profile_select(None)
     elapsed = t1 - t0
     ms_step = 1e3 * elapsed / args.steps
-    value = updates_per_step * args.steps / elapsed
-    total_bytes = sum(v["algo_bytes"] for v in kern.values())
-    log(f"bench: {ms_step:.3f} ms/step, {value:.4e} amp-updates/s, cut {res.cut}")
+    value = W["updates"] * args.steps / elapsed
+    log(f"bench: {ms_step:.3f} ms/step, {value:.4e} amp-updates/s")
+    log("bench: kernels of the profiled warm-up step:")
     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"]):
         gbs = v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9 if v["total_ms"] > 0 else 0.0
         log(f"  {k:11s} {v['launches']:6d} launches  avg {v['avg_us']:9.2f} us  {gbs:8.1f} GB/s algorithmic")
 
-    dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    d = kern[dom]
+    d = timed[dom]
+    log(f"bench: timed region: {dom} {d['launches']} launches, avg {d['avg_us']:.2f} us")
     achieved = d["algo_bytes"] / (d["total_ms"] * 1e-3) / 1e9
-    tr = traffic_record(dom)
+    tr = traffic_record(dom, args.workload) if args.mixer == "valu" else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "algo_bytes_per_launch": d["algo_bytes"] / d["launches"], "avg_launch_us": round(d["avg_us"], 2),
@@ -143,35 +281,20 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "amp-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": "plain-method solve, G(400,0.05) seed 0, 21 subgraphs x 20 qubits, p=3, "
-                               "50 Adam steps, top-16, beam 4096, CutVal",
-                   "graph_replay": bool(args.graph),
-                   "vertices": 400, "edges": g.num_edges, "subgraphs": part.M, "qubits": 20, "p": cfg.p,
-                   "adam_steps": cfg.iters, "k": cfg.k, "beam": cfg.beam},
-        "hbm_gbs_step": total_bytes / args.steps / (elapsed / args.steps) / 1e9,
+        "vs_baseline": None, "dtype": W["dtype"], "data": "synthetic", "config": W["config"],
         "roofline": roofline,
-        "solve": {"cut": res.cut, "sum_E": float(np.sum(res.energies))},
-        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
-                        "algo_GBs": round(v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] else 0}
-                    for k, v in kern.items()},
     }
-    S.close()
-
+    out.update(W["summary"]())
+    out["kernels_warmup_step"] = {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
+                                      "algo_GBs": round(v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
+                                      if v["total_ms"] else 0} for k, v in kern.items()}
+    if args.workload == "ragged2000":
+        out["solve_seconds"] = ms_step / 1e3
+    W["close"]()
     if not args.no_cpu_baseline:
-        import oracle
-        g0, b0 = cold_start(cfg.p, part.M)
-        T = args.cpu_iters
-        log(f"bench: CPU baseline: FP64 oracle, {part.M} subgraphs x ({T} Adam steps + final evaluation)")
-        c0 = time.perf_counter()
-        oracle.solve_batch(part.size, S.sub_edges, g0, b0, T, cfg.k, lr=cfg.lr)
-        c1 = time.perf_counter()
-        cpu_value = (3 * T + 1) * U / (c1 - c0)
-        out["cpu_baseline"] = {"value": cpu_value, "unit": "amp-updates/s", "cores": oracle.num_threads(),
-                               "kind": "oracle", "seconds": round(c1 - c0, 2),
-                               "sample": f"all {part.M} subgraphs of the 400-vertex workload, {T} Adam steps "
-                                         f"with adjoint gradients + final evaluation and top-{cfg.k} (FP64)"}
-        log(f"bench: CPU baseline {cpu_value:.4e} amp-updates/s in {c1 - c0:.1f} s on {oracle.num_threads()} threads")
+        cb = W["cpu_baseline"]()
+        out["cpu_baseline"] = cb
+        log(f"bench: CPU baseline {cb['value']:.4e} amp-updates/s in {cb['seconds']} s on {cb['cores']} threads")
     print(json.dumps(out), flush=True)
 
 

@@ -272,6 +272,10 @@ const char* qaoa_last_error(void);
  * algorithmic bytes since the last qaoa_profile_enable(1). Not for use while
  * another thread launches. */
 qaoa_status_t qaoa_profile_enable(int32_t on);
+/* Restrict the timing to one kernel name (NULL or "" = all). Each timed launch
+ * adds two event records to its stream; timing only the kernel of interest
+ * keeps that cost off the others. */
+qaoa_status_t qaoa_profile_select(const char* kernel);
 qaoa_status_t qaoa_profile_read(const char* kernel, int64_t* launches, double* total_ms, double* algo_bytes);
 
 #ifdef __cplusplus

@@ -78,6 +78,7 @@ def lib() -> ct.CDLL:
             "qaoa_state_offset": [_vp, _i32, _vp],
             "qaoa_profile_enable": [_i32],
             "qaoa_profile_read": [ct.c_char_p, _vp, _vp, _vp],
+            "qaoa_profile_select": [ct.c_char_p],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -227,6 +228,11 @@ def qaoa_state_offset(h: int, b: int) -> int:
 
 def qaoa_profile_enable(on: int) -> None:
     _call("qaoa_profile_enable", int(on))
+
+
+def qaoa_profile_select(kernel) -> None:
+    """Time only `kernel` (None = every kernel)."""
+    _call("qaoa_profile_select", None if kernel is None else kernel.encode())
 
 
 def qaoa_profile_read(kernel: str):

@@ -50,6 +50,7 @@ struct ProfRec {
 };
 struct Profiler {
     bool on = false;
+    std::string only;  // empty: every kernel; else only this name is timed
     std::map<std::string, std::vector<ProfRec>> recs;
     std::map<std::string, double> bytes;  // algorithmic bytes of the recorded launches
     std::vector<ProfRec> pool;
@@ -61,7 +62,8 @@ struct ProfScope {
     hipStream_t s;
     ProfRec r{};
     bool active;
-    ProfScope(const char* n, hipStream_t st, double algo_bytes = 0.0) : name(n), s(st), active(g_prof.on)
+    ProfScope(const char* n, hipStream_t st, double algo_bytes = 0.0)
+        : name(n), s(st), active(g_prof.on && (g_prof.only.empty() || g_prof.only == n))
     {
         if (!active) return;
         g_prof.bytes[name] += algo_bytes;
@@ -69,8 +71,9 @@ struct ProfScope {
             r = g_prof.pool.back();
             g_prof.pool.pop_back();
         } else {
-            (void)hipEventCreate(&r.a);
-            (void)hipEventCreate(&r.b);
+            // timing only: no system-scope fence (no cache writeback between kernels)
+            (void)hipEventCreateWithFlags(&r.a, hipEventDisableSystemFence);
+            (void)hipEventCreateWithFlags(&r.b, hipEventDisableSystemFence);
         }
         (void)hipEventRecord(r.a, s);
     }
@@ -93,6 +96,12 @@ extern "C" qaoa_status_t qaoa_profile_enable(int32_t on)
     g_prof.recs.clear();
     g_prof.bytes.clear();
     g_prof.on = on != 0;
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_profile_select(const char* kernel)
+{
+    g_prof.only = kernel ? kernel : "";
     return ok();
 }
 
