@@ -215,40 +215,50 @@ __global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* ke
     __syncthreads();
     const int64_t star = s_star;
     const int32_t R = s_R;
-    // compaction in index order: thread t owns the chunk [t*C, (t+1)*C)
-    const int64_t C = (N + SEL_THREADS - 1) / SEL_THREADS;
-    const int64_t lo = (int64_t)tid * C, up = lo + C < N ? lo + C : N;
+    // compaction in index order: wave w owns keys [w*S, (w+1)*S), read 64
+    // consecutive keys at a time; ballots give each lane its rank among the
+    // wave's keys above / at the threshold, one barrier gives the wave bases
+    __shared__ int32_t wgt[SEL_THREADS / 64], weq[SEL_THREADS / 64];
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int NWV = SEL_THREADS / 64;
+    const int64_t S = (N + NWV - 1) / NWV;
+    const int64_t lo = (int64_t)wv * S, up = lo + S < N ? lo + S : N;
+    const uint64_t below = (1ull << lane) - 1ull;
     int32_t gt = 0, eq = 0;
-    for (int64_t q = lo; q < up; ++q) {
-        const uint64_t k = keys[q];
-        if (!k) continue;
-        const int64_t sc = key_score(k);
-        gt += sc > star;
-        eq += sc == star;
+    for (int64_t base = lo; base < up; base += 64) {
+        const int64_t q = base + lane;
+        const uint64_t k = q < up ? keys[q] : 0ull;
+        const int64_t sc = k ? key_score(k) : 0;
+        gt += __popcll(__ballot(k && sc > star));
+        eq += __popcll(__ballot(k && sc == star));
     }
-    int32_t tot;
-    int32_t gt_before = block_exscan(gt, buf, &tot);
-    int32_t eq_before = block_exscan(eq, buf, &tot);
-    for (int64_t q = lo; q < up; ++q) {
-        const uint64_t k = keys[q];
-        if (!k) continue;
-        const int64_t sc = key_score(k);
-        bool take = false;
-        if (sc > star) {
-            take = true;
-        } else if (sc == star) {
-            take = eq_before < R;
-        }
-        if (take) {
-            const int pos = gt_before + (eq_before < R ? eq_before : R);
+    if (lane == 0) {
+        wgt[wv] = gt;
+        weq[wv] = eq;
+    }
+    __syncthreads();
+    int32_t gt_before = 0, eq_before = 0;
+    for (int w = 0; w < wv; ++w) {
+        gt_before += wgt[w];
+        eq_before += weq[w];
+    }
+    for (int64_t base = lo; base < up; base += 64) {
+        const int64_t q = base + lane;
+        const uint64_t k = q < up ? keys[q] : 0ull;
+        const int64_t sc = k ? key_score(k) : 0;
+        const bool g = k && sc > star, e = k && sc == star;
+        const uint64_t bg = __ballot(g), be = __ballot(e);
+        const int32_t my_gt = gt_before + __popcll(bg & below), my_eq = eq_before + __popcll(be & below);
+        if (g || (e && my_eq < R)) {
+            const int pos = my_gt + (my_eq < R ? my_eq : R);
             Surv sv;
             sv.parent = first ? 0 : (int32_t)(q / Kmul);
             sv.digit = first ? (int32_t)q : (int32_t)(q % Kmul);
             sv.score = sc;
             surv[pos] = sv;
         }
-        if (sc > star) ++gt_before;
-        else if (sc == star) ++eq_before;
+        gt_before += __popcll(bg);
+        eq_before += __popcll(be);
     }
     if (tid == 0) *nsurv = count;
 }
