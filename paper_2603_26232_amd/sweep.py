@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import time
 
@@ -78,7 +79,7 @@ def sweep(name, Ks, Ws, iters=50, log=print):
         for W in Ws:
             ms, cut = time_merge(g, part, cand, K, W)
             rows.append({"K": K, "W": W, "cut": cut, "merge_ms": ms,
-                         "exact": bool(W >= 2 * float(K) ** (part.M - 1))})
+                         "exact": bool(math.log2(W) >= 1 + (part.M - 1) * math.log2(K))})
             log(f"sweep: {name} K={K:3d} W={W:5d} cut {cut} merge {ms:.3f} ms")
     S.close()
     return {"workload": name, "vertices": g.num_vertices, "edges": g.num_edges, "subgraphs": part.M,
