@@ -188,6 +188,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the Adam step from a captured HIP graph")
+    ap.add_argument("--tuning", default="default",
+                    help="group-split tuning table (JSON from paper_2603_26232_amd.autotune); 'default' = the "
+                         "package's table if present, 'none' = untuned")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration, copy bandwidth)")
     args = ap.parse_args()
@@ -220,7 +223,13 @@ def main():
             f"{2 * n / (ms * 1e-3) / 1e9:.1f} GB/s")
         return
 
+    from paper_2603_26232_amd import autotune
+    tuned = {} if args.tuning == "none" else autotune.apply(
+        autotune.DEFAULT_TABLE if args.tuning == "default" else args.tuning)
+    if tuned:
+        log(f"bench: tuned group splits {tuned}")
     W = workload_precision(args) if args.workload == "precision26" else workload_solve(args, args.workload)
+    W["config"]["tuned_group_splits"] = {str(k): v for k, v in tuned.items()}
     step = W["step"]
 
     def read_profile():

@@ -255,6 +255,18 @@ qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_t hidden, i
  * an intermediate of the adjoint sweep. For inspection and tests. */
 qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* out_offset);
 
+/* Tuning of the strided qubit groups (process-wide, read when a batch is
+ * created). Subgraphs with n > 12 qubits split them into group 0 (qubits
+ * 0..11, contiguous tiles) and strided groups of at most 8 qubits, one HBM pass
+ * per group and layer (Sec. 2.2's mixer is a product over qubits, so any
+ * grouping gives the same state). sizes[0..count) are the strided group sizes
+ * in qubit order for subgraphs with n qubits (each 1..8, at most 3 groups,
+ * adding up to n - 12); count = 0 restores the default (fewest groups, sizes
+ * as even as possible). Batches created earlier keep their layout.
+ * QAOA_ERR_OUT_OF_RANGE for n outside 13..30, count > 3 or a size outside
+ * 1..8; QAOA_ERR_INVALID_ARG if the sizes do not add up to n - 12. */
+qaoa_status_t qaoa_tune_group_split(int32_t n, int32_t count, const int32_t* sizes);
+
 /* Text of a status code (static storage). */
 const char* qaoa_status_string(qaoa_status_t s);
 

@@ -79,6 +79,7 @@ def lib() -> ct.CDLL:
             "qaoa_profile_enable": [_i32],
             "qaoa_profile_read": [ct.c_char_p, _vp, _vp, _vp],
             "qaoa_profile_select": [ct.c_char_p],
+            "qaoa_tune_group_split": [_i32, _i32, _vp],
         }
         for name, args in sig.items():
             if not hasattr(L, name):
@@ -228,6 +229,13 @@ def qaoa_state_offset(h: int, b: int) -> int:
 
 def qaoa_profile_enable(on: int) -> None:
     _call("qaoa_profile_enable", int(on))
+
+
+def qaoa_tune_group_split(n: int, sizes) -> None:
+    """Strided group sizes for n-qubit subgraphs of batches created from now
+    on (empty / None = default split)."""
+    arr = np.ascontiguousarray(sizes if sizes else [0], dtype=np.int32)
+    _call("qaoa_tune_group_split", int(n), len(sizes) if sizes else 0, arr.ctypes.data_as(ct.c_void_p))
 
 
 def qaoa_profile_select(kernel) -> None:

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -173,6 +174,23 @@ int groups_for(int n)
     return 1 + (rest + B_GROUP_MAX - 1) / B_GROUP_MAX;
 }
 
+// Tuned sizes of the strided qubit groups per qubit count (empty = even
+// split into the fewest groups); read when a batch is planned.
+std::mutex g_split_mu;
+std::vector<int> g_split[QAOA_MAX_QUBITS + 1];
+
+std::vector<int> group_split(int n)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_split_mu);
+        if (!g_split[n].empty()) return g_split[n];
+    }
+    std::vector<int> v;
+    const int G1 = groups_for(n) - 1, rest = n - TILE_BITS;
+    for (int g = 1; g <= G1; ++g) v.push_back(rest / G1 + (g <= rest % G1 ? 1 : 0));
+    return v;
+}
+
 qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const int32_t* ew, int32_t max_p,
                         int32_t max_k, uint32_t flags, Plan& P)
 {
@@ -214,17 +232,16 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
                         QAOA_MAX_WEIGHT_SUM);
         SubDesc& d = P.subs[b];
         d.n = n;
-        d.ngroups = groups_for(n);
         d.gstart[0] = 0;
         d.gsize[0] = n < TILE_BITS ? n : TILE_BITS;
-        if (d.ngroups > 1) {
-            const int rest = n - TILE_BITS, G1 = d.ngroups - 1;
+        d.ngroups = 1;
+        if (n > SMALL_MAX_N) {
             int q = TILE_BITS;
-            for (int g = 1; g <= G1; ++g) {
-                const int sz = rest / G1 + (g <= rest % G1 ? 1 : 0);
-                d.gstart[g] = q;
-                d.gsize[g] = sz;
+            for (int sz : group_split(n)) {
+                d.gstart[d.ngroups] = q;
+                d.gsize[d.ngroups] = sz;
                 q += sz;
+                ++d.ngroups;
             }
         }
         d.lut_len = (int32_t)wsum + 1;
@@ -396,6 +413,28 @@ double small_bytes(const Plan& P, int p, bool grad)
 }
 
 }  // namespace
+
+extern "C" qaoa_status_t qaoa_tune_group_split(int32_t n, int32_t count, const int32_t* sizes)
+{
+    if (n <= SMALL_MAX_N || n > QAOA_MAX_QUBITS)
+        return fail(QAOA_ERR_OUT_OF_RANGE, "n = %d outside %d..%d", n, SMALL_MAX_N + 1, QAOA_MAX_QUBITS);
+    if (count < 0 || count > MAX_GROUPS - 1)
+        return fail(QAOA_ERR_OUT_OF_RANGE, "count = %d outside 0..%d", count, MAX_GROUPS - 1);
+    std::vector<int> v;
+    int sum = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!sizes) return fail(QAOA_ERR_INVALID_ARG, "sizes is NULL");
+        if (sizes[i] < 1 || sizes[i] > B_GROUP_MAX)
+            return fail(QAOA_ERR_OUT_OF_RANGE, "group size %d outside 1..%d", sizes[i], B_GROUP_MAX);
+        v.push_back(sizes[i]);
+        sum += sizes[i];
+    }
+    if (count > 0 && sum != n - TILE_BITS)
+        return fail(QAOA_ERR_INVALID_ARG, "group sizes add up to %d, not n - %d = %d", sum, TILE_BITS, n - TILE_BITS);
+    std::lock_guard<std::mutex> lk(g_split_mu);
+    g_split[n] = v;
+    return ok();
+}
 
 // ---------------------------------------------------------------------------
 // handle

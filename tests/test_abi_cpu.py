@@ -148,3 +148,14 @@ def test_mixer_precision_flags():
     with pytest.raises(_abi.QaoaError) as ei:
         _ws([16], [e], flags=_abi.QAOA_FLAG_MIXER_MFMA_BF16X3 | _abi.QAOA_FLAG_MIXER_MFMA_BF16X4)
     assert ei.value.status == 1
+
+
+def test_group_split_tuning_validation():
+    _abi.qaoa_tune_group_split(26, [6, 8])
+    _abi.qaoa_tune_group_split(26, [2, 4, 8])
+    _abi.qaoa_tune_group_split(26, None)  # back to the default
+    for n, sizes, status in [(26, [7, 8], 1), (12, [1], 2), (31, [8, 8, 3], 2), (26, [9, 5], 2),
+                             (30, [6, 6, 6, 0], 2)]:
+        with pytest.raises(_abi.QaoaError) as ei:
+            _abi.qaoa_tune_group_split(n, sizes)
+        assert ei.value.status == status, (n, sizes)

@@ -259,3 +259,27 @@ def test_skip_edgeless_matches_simulation():
         assert np.allclose(p0[b], 2.0 ** -n, rtol=1e-5, atol=0) and np.all(i0[b] % 2 == 0)
     ref.close()
     skp.close()
+
+
+@pytest.mark.parametrize("n,split", [(21, [1, 8]), (21, [8, 1]), (21, [3, 3, 3]), (26, [6, 8]), (26, [8, 6]),
+                                     (24, [4, 8]), (16, [1, 1, 2])])
+def test_tuned_group_splits(n, split):
+    """Any split of the strided qubits into groups gives the same state."""
+    from paper_2603_26232_amd import _abi
+    edges = _subgraphs([n], 700 + n, p_edge=0.2)
+    gamma, beta = synth.uniform_angles(7000 + n, 2, batch=1)
+    _abi.qaoa_tune_group_split(n, split)
+    try:
+        bt = QaoaBatch([n], edges, max_p=2, max_k=8, gradient=True)
+    finally:
+        _abi.qaoa_tune_group_split(n, None)
+    bt.apply_layers(gamma, beta)
+    _check_states(bt, [n], edges, gamma, beta)
+    E, dg, db = bt.expectation_grad(gamma, beta)
+    u, v, w = edges[0]
+    C = oracle.cut_table(n, u, v, w)
+    e_ref, g_ref, b_ref = oracle.gradient(n, C, gamma[0], beta[0])
+    scale = max(1.0, float(np.abs(np.concatenate([g_ref, b_ref])).max()))
+    assert np.max(np.abs(dg.cpu().numpy()[0] - g_ref)) <= G_TOL * scale
+    assert np.max(np.abs(db.cpu().numpy()[0] - b_ref)) <= G_TOL * scale
+    bt.close()
