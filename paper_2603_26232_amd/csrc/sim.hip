@@ -921,27 +921,30 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
 __global__ __launch_bounds__(THREADS) void k_reduce(const SubDesc* subs, int p, int grad, Partials part,
                                                     double* E, double* dgamma, double* dbeta)
 {
+    // block (b, q): q = 0 sums <C>, q = 1..p the gamma term of layer q - 1,
+    // q = p + 1..2p the beta terms of layer q - p - 1 (over every group)
     __shared__ double red[THREADS / 64];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x, q = blockIdx.y;
     const SubDesc* sd = subs + b;
     const int T = part.total_tiles, tb = sd->tile_base, nt = sd->ntiles, G = sd->ngroups;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.e[tb + i];
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0 && E) E[b] = acc;
-    if (!grad) return;
-    for (int l = 0; l < p; ++l) {
-        double xb = 0.0;
+    if (q == 0) {
+        for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.e[tb + i];
+    } else if (q <= p) {
+        for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.gg[(size_t)(q - 1) * T + tb + i];
+    } else {
+        const int l = q - p - 1;
         for (int g = 0; g < G; ++g)
-            for (int i = threadIdx.x; i < nt; i += THREADS)
-                xb += part.gb[((size_t)l * MAX_GROUPS + g) * T + tb + i];
-        xb = block_sum(xb, red);
-        double gg = 0.0;
-        for (int i = threadIdx.x; i < nt; i += THREADS) gg += part.gg[(size_t)l * T + tb + i];
-        gg = block_sum(gg, red);
-        if (threadIdx.x == 0) {
-            dbeta[(size_t)b * p + l] = 2.0 * xb;
-            dgamma[(size_t)b * p + l] = 2.0 * gg;
+            for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.gb[((size_t)l * MAX_GROUPS + g) * T + tb + i];
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+        if (q == 0) {
+            if (E) E[b] = acc;
+        } else if (q <= p) {
+            dgamma[(size_t)b * p + q - 1] = 2.0 * acc;
+        } else {
+            dbeta[(size_t)b * p + q - p - 1] = 2.0 * acc;
         }
     }
 }
@@ -1037,7 +1040,8 @@ hipError_t launch_small(uint8_t* ws, const SubDesc* subs, const int32_t* list, i
 hipError_t launch_reduce(const SubDesc* subs, int B, int p, int grad, Partials part, double* E,
                          double* dgamma, double* dbeta, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(B), dim3(THREADS), 0, s, subs, p, grad, part, E, dgamma, dbeta);
+    hipLaunchKernelGGL(k_reduce, dim3(B, grad ? 1 + 2 * p : 1), dim3(THREADS), 0, s, subs, p, grad, part, E, dgamma,
+                       dbeta);
     return hipGetLastError();
 }
 
