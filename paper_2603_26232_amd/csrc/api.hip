@@ -152,6 +152,7 @@ struct Plan {
         int chain[MAX_GROUPS];
         std::vector<int2> work;
         uint64_t o_work;
+        double tab_bytes;  // cut-table bytes of one pass over the class's tiles
     };
     std::vector<Class> classes;
 };
@@ -245,6 +246,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
             }
         }
         d.lut_len = (int32_t)wsum + 1;
+        d.tabw = wsum <= 255 ? 1 : 2;
         d.skip = (flags & QAOA_FLAG_SKIP_EDGELESS) && eoff[b + 1] == eoff[b];
         d.ntiles = d.skip ? 0 : (n > TILE_BITS ? (1 << (n - TILE_BITS)) : 1);
         d.tile_base = (int32_t)tiles;
@@ -283,6 +285,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
                 ci = (int)P.classes.size() - 1;
             }
             for (int t = 0; t < d.ntiles; ++t) P.classes[ci].work.push_back(make_int2(b, t));
+            P.classes[ci].tab_bytes += (double)d.ntiles * TILE * d.tabw;
         }
     }
     for (int b = 0; b < B; ++b)
@@ -321,8 +324,8 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
         if (d.skip) continue;  // closed form, nothing stored
         d.psi = region(dim * sizeof(float2), 4096);
         d.lam = grad ? region(dim * sizeof(float2), 4096) : 0;
-        d.tab = region(dim * sizeof(uint16_t), 4096);
-        d.tabB = d.ngroups >= 2 ? region(dim * sizeof(uint16_t), 4096) : 0;
+        d.tab = region(dim * (uint64_t)d.tabw, 4096);
+        d.tabB = d.ngroups >= 2 ? region(dim * (uint64_t)d.tabw, 4096) : 0;
     }
     (void)eo;
     P.total = align_up(o, 4096);
@@ -381,18 +384,24 @@ std::vector<PassOps> group_passes(const std::vector<Op>& ops)
 // Algorithmic HBM bytes of one tile pass: every state it touches read once
 // and written once (complex64, 8 B per amplitude) plus the uint16 cut table
 // when the pass needs C(z).
-double pass_bytes(const PassOps& o, bool backward, int nwork)
+// algorithmic HBM bytes of one pass over a class: states read and written
+// once, the cut table (1 or 2 B per amplitude) where the pass needs C(z)
+double pass_bytes(const PassOps& o, bool backward, int nwork, double tab_bytes)
 {
     const double amps = (double)nwork * TILE;
     double per;
+    bool tab;
     if (!backward) {
-        per = (o.init ? 8.0 : 16.0) + ((o.ph >= 0 || o.epi_e) ? 2.0 : 0.0);
+        per = o.init ? 8.0 : 16.0;
+        tab = o.ph >= 0 || o.epi_e;
     } else if (o.fused) {
-        per = 8.0 + 8.0 + 2.0;  // read psi, write lambda, cut table
+        per = 8.0 + 8.0;  // read psi, write lambda
+        tab = true;
     } else {
-        per = 16.0 + (o.last ? 0.0 : 16.0) + (o.ph >= 0 ? 2.0 : 0.0);
+        per = 16.0 + (o.last ? 0.0 : 16.0);
+        tab = o.ph >= 0;
     }
-    return per * amps;
+    return per * amps + (tab ? tab_bytes : 0.0);
 }
 
 double angle_bytes(const Plan& P, int p)
@@ -408,7 +417,7 @@ double small_bytes(const Plan& P, int p, bool grad)
 {
     double b = 0.0;
     for (const SubDesc& d : P.subs)
-        if (d.ngroups == 1 && !d.skip) b += (double)(1ull << d.n) * (grad ? 2.0 * (2 * p + 2) : (2.0 * (p + 1) + 8.0));
+        if (d.ngroups == 1 && !d.skip) b += (double)(1ull << d.n) * (grad ? d.tabw * (2.0 * p + 2) : (d.tabw * (p + 1.0) + 8.0));
     return b;
 }
 
@@ -587,7 +596,7 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
             PassOps o = passes[i];
             o.init = i == 0;
             o.epi_e = i + 1 == passes.size();
-            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
+            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw, c.tab_bytes));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, P.prec,
                                     st));
         }
@@ -654,7 +663,7 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         for (size_t i = 0; i + 1 < fwd.size(); ++i) {
             PassOps o = fwd[i];
             o.init = i == 0;
-            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw));
+            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw, c.tab_bytes));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, 0, st));
         }
         std::vector<Op> rev(ops.rbegin(), ops.rend());
@@ -664,13 +673,13 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         PassOps f = fwd.back();
         f.fused = 1;
         {
-            ProfScope ps("bwd_pass", st, pass_bytes(f, true, nw));
+            ProfScope ps("bwd_pass", st, pass_bytes(f, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[f.group], f, h->part, P.lut_max, st));
         }
         for (size_t i = 1; i < bwd.size(); ++i) {
             PassOps o = bwd[i];
             o.last = i + 1 == bwd.size();
-            ProfScope ps("bwd_pass", st, pass_bytes(o, true, nw));
+            ProfScope ps("bwd_pass", st, pass_bytes(o, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }
     }

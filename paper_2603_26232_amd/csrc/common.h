@@ -35,7 +35,7 @@ struct SubDesc {
     int32_t tile_base;  // first global tile index
     int32_t nedges;
     int32_t skip;  // edgeless and not simulated (closed form)
-    int32_t pad1;
+    int32_t tabw;  // bytes per cut-table entry: 1 (weight sum <= 255) or 2
     uint64_t psi, lam, tab, tabB, lut, coef, edges;  // byte offsets into the workspace
 };
 

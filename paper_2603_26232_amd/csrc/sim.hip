@@ -418,12 +418,34 @@ __device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* l
 // C(z) for the 16 amplitudes a lane holds in layout L, for data permuted by
 // the flip mask m (slot q holds amplitude q ^ m). Group 0 reads the natural
 // table, the last group its tile-order copy (contiguous per tile).
+// A subgraph's cut table: 1 byte per entry when its weight sum is at most
+// 255, else 2 (the width is uniform per workgroup).
+struct CutTab {
+    const uint8_t* p;
+    int w;
+    __device__ uint32_t at(uint32_t i) const { return w == 1 ? (uint32_t)p[i] : (uint32_t)((const uint16_t*)p)[i]; }
+};
+
 template <int L>
-__device__ inline void load_cut_L(uint16_t (&cr)[REGS], const uint16_t* tab, uint32_t tid, uint32_t m)
+__device__ inline void load_cut_L(uint16_t (&cr)[REGS], const CutTab& tab, uint32_t tid, uint32_t m)
 {
     const uint32_t tp = thread_part<L>(tid) ^ m;
+    if (tab.w == 1) {
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) cr[r] = tab[tp ^ reg_part<L>(r)];
+        for (int r = 0; r < REGS; ++r) cr[r] = tab.p[tp ^ reg_part<L>(r)];
+    } else {
+        const uint16_t* t16 = (const uint16_t*)tab.p;
+#pragma unroll
+        for (int r = 0; r < REGS; ++r) cr[r] = t16[tp ^ reg_part<L>(r)];
+    }
+}
+
+// the tile's slice of the table: natural order for group 0, the tile-ordered
+// copy for the last group
+__device__ inline CutTab tile_tab(const uint8_t* ws, const SubDesc* sd, int g, const Geo& geo, uint32_t t)
+{
+    const int w = sd->tabw;
+    return CutTab{g == 0 ? ws + sd->tab + (size_t)geo.zb * w : ws + sd->tabB + (size_t)t * TILE * w, w};
 }
 
 template <int L>
@@ -529,15 +551,23 @@ __global__ __launch_bounds__(THREADS) void k_cut_tables(uint8_t* ws, const SubDe
     const uint32_t t = (uint32_t)wk.y;
     const int n = sd->n, ne = sd->nedges, G = sd->ngroups;
     const int32_t* E = (const int32_t*)(ws + sd->edges);
-    uint16_t* tab = (uint16_t*)(ws + sd->tab);
+    uint8_t* tab = ws + sd->tab;
     const uint32_t dim = 1u << n;
     const uint32_t span = dim < (uint32_t)TILE ? dim : (uint32_t)TILE;
     const Geo geo = make_geo(sd, G >= 2 ? G - 1 : 0, t);
-    uint16_t* tabB = (uint16_t*)(ws + sd->tabB);
+    uint8_t* tabB = ws + sd->tabB;
+    const bool w1 = sd->tabw == 1;
     for (uint32_t q = threadIdx.x; q < span; q += THREADS) {
         const uint32_t z = t * TILE + q;
-        tab[z] = (uint16_t)cut_of(z, E, ne);
-        if (G >= 2) tabB[(size_t)t * TILE + q] = (uint16_t)cut_of(geo.zb | gmap(geo, q), E, ne);
+        const uint32_t c = cut_of(z, E, ne);
+        if (w1) tab[z] = (uint8_t)c;
+        else ((uint16_t*)tab)[z] = (uint16_t)c;
+        if (G >= 2) {
+            const uint32_t cb = cut_of(geo.zb | gmap(geo, q), E, ne);
+            const size_t i = (size_t)t * TILE + q;
+            if (w1) tabB[i] = (uint8_t)cb;
+            else ((uint16_t*)tabB)[i] = (uint16_t)cb;
+        }
     }
 }
 
@@ -625,8 +655,7 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     float2* st = (float2*)(ws + sd->psi);
     const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
     const int lut_len = sd->lut_len;
-    const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + sd->tab) + geo.zb
-                                   : (const uint16_t*)(ws + sd->tabB) + (size_t)t * TILE;
+    const CutTab tab = tile_tab(ws, sd, g, geo, t);
     const uint32_t gb = group_bits(geo.c);
     RxC pre{}, post{};
     if constexpr (HAS_PRE) pre = load_rx(cf, ops.pre, g);
@@ -726,8 +755,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     const int lut_len = sd->lut_len;
     const int T = part.total_tiles;
     const int tile = sd->tile_base + (int)t;
-    const uint16_t* tab = (g == 0) ? (const uint16_t*)(ws + sd->tab) + geo.zb
-                                   : (const uint16_t*)(ws + sd->tabB) + (size_t)t * TILE;
+    const CutTab tab = tile_tab(ws, sd, g, geo, t);
     const uint32_t gb = group_bits(geo.c);
     const RxC pre = load_rx(cf, ops.pre, g);
     RxC post{};
@@ -839,7 +867,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
     float2* ps = smem;
     float2* la = smem + TILE;
     float2* lut = smem + (grad ? 2 * TILE : TILE);
-    const uint16_t* tab = (const uint16_t*)(ws + sd->tab);
+    const CutTab tab{ws + sd->tab, sd->tabw};
     const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
     const float2* luts = (const float2*)(ws + sd->lut);
     const int lut_len = sd->lut_len;
@@ -852,7 +880,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
         __syncthreads();
         for (int i = tid; i < lut_len; i += THREADS) lut[i] = luts[(size_t)l * lut_len + i];
         __syncthreads();
-        for (uint32_t z = tid; z < dim; z += THREADS) ps[z] = cmul(ps[z], lut[tab[z]]);
+        for (uint32_t z = tid; z < dim; z += THREADS) ps[z] = cmul(ps[z], lut[tab.at(z)]);
         const float2 cs = cf[l].cs;
         for (int j = 0; j < n; ++j) {
             __syncthreads();
@@ -865,7 +893,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
     __syncthreads();
     double acc = 0.0;
     for (uint32_t z = tid; z < dim; z += THREADS)
-        acc += ((double)ps[z].x * ps[z].x + (double)ps[z].y * ps[z].y) * (double)tab[z];
+        acc += ((double)ps[z].x * ps[z].x + (double)ps[z].y * ps[z].y) * (double)tab.at(z);
     acc = block_sum(acc, red);
     if (tid == 0) part.e[tile] = acc;
     if (!grad) {
@@ -874,7 +902,7 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
         return;
     }
     for (uint32_t z = tid; z < dim; z += THREADS) {
-        const float c = (float)tab[z];
+        const float c = (float)tab.at(z);
         la[z] = make_float2(c * ps[z].x, c * ps[z].y);
     }
     for (int l = p - 1; l >= 0; --l) {
@@ -898,14 +926,14 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
         if (tid == 0) part.gb[((size_t)l * MAX_GROUPS + 0) * T + tile] = xb;
         double gg = 0.0;
         for (uint32_t z = tid; z < dim; z += THREADS)
-            gg += (double)((float)tab[z] * (la[z].x * ps[z].y - la[z].y * ps[z].x));
+            gg += (double)((float)tab.at(z) * (la[z].x * ps[z].y - la[z].y * ps[z].x));
         gg = block_sum(gg, red);
         if (tid == 0) part.gg[(size_t)l * T + tile] = gg;
         if (l > 0) {
             for (int i = tid; i < lut_len; i += THREADS) lut[i] = luts[(size_t)l * lut_len + i];
             __syncthreads();
             for (uint32_t z = tid; z < dim; z += THREADS) {
-                float2 f = lut[tab[z]];
+                float2 f = lut[tab.at(z)];
                 f.y = -f.y;
                 ps[z] = cmul(ps[z], f);
                 la[z] = cmul(la[z], f);

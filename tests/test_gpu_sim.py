@@ -286,3 +286,30 @@ def test_tuned_group_splits(n, split):
     assert np.max(np.abs(dg.cpu().numpy()[0] - g_ref)) <= G_TOL * scale
     assert np.max(np.abs(db.cpu().numpy()[0] - b_ref)) <= G_TOL * scale
     bt.close()
+
+
+def test_wide_cut_tables():
+    """Weight sums above 255 use 2-byte cut tables (1 byte otherwise); both
+    widths in one batch, tile path and whole-state path."""
+    sizes = [16, 21, 10, 14]
+    edges = []
+    for i, n in enumerate(sizes):
+        g = synth.erdos_renyi(n, 0.3, 900 + i)
+        w = synth.random_weights(g.num_edges, 950 + i, 10, 20) if i % 2 == 0 else g.w
+        while w.sum() > 2047:
+            w = np.maximum(1, w // 2).astype(np.int32)
+        edges.append((g.u, g.v, w))
+    assert edges[0][2].sum() > 255 and edges[1][2].sum() <= 255
+    gamma, beta = synth.uniform_angles(9000, 2, batch=len(sizes))
+    bt = QaoaBatch(sizes, edges, max_p=2, max_k=8, gradient=True)
+    bt.apply_layers(gamma, beta)
+    _check_states(bt, sizes, edges, gamma, beta)
+    E, dg, db = bt.expectation_grad(gamma, beta)
+    for b, n in enumerate(sizes):
+        u, v, w = edges[b]
+        C = oracle.cut_table(n, u, v, w)
+        e_ref, g_ref, b_ref = oracle.gradient(n, C, gamma[b], beta[b])
+        scale = max(1.0, float(np.abs(np.concatenate([g_ref, b_ref])).max()))
+        assert np.max(np.abs(dg.cpu().numpy()[b] - g_ref)) <= G_TOL * scale
+        assert np.max(np.abs(db.cpu().numpy()[b] - b_ref)) <= G_TOL * scale
+    bt.close()
