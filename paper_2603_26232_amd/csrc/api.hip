@@ -397,8 +397,11 @@ double pass_bytes(const PassOps& o, bool backward, int nwork, double tab_bytes)
     } else if (o.fused) {
         per = 8.0 + 8.0;  // read psi, write lambda
         tab = true;
+    } else if (o.last) {
+        per = 8.0;  // read lambda (psi is synthesised)
+        tab = true;
     } else {
-        per = 16.0 + (o.last ? 0.0 : 16.0);
+        per = 16.0 + (o.nopsi ? 8.0 : 16.0);
         tab = o.ph >= 0;
     }
     return per * amps + (tab ? tab_bytes : 0.0);
@@ -679,6 +682,7 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         for (size_t i = 1; i < bwd.size(); ++i) {
             PassOps o = bwd[i];
             o.last = i + 1 == bwd.size();
+            o.nopsi = i + 2 == bwd.size();  // the last pass synthesises psi
             ProfScope ps("bwd_pass", st, pass_bytes(o, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }

@@ -48,7 +48,8 @@ struct PassOps {
     int32_t init;      // forward: synthesise |+> instead of loading
     int32_t epi_e;     // forward: write the <C> partial of each tile
     int32_t fused;     // backward: forward RX(pre) + <C> + lambda = C psi first
-    int32_t last;      // backward: nothing needs storing
+    int32_t last;      // backward: the inverse of the first forward pass; nothing stored
+    int32_t nopsi;     // backward: psi is not needed after this pass (not stored)
 };
 
 // Rotation parameters of one layer of one subgraph: e^{-i beta X} =

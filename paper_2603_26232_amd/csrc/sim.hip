@@ -415,6 +415,40 @@ __device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* l
     }
 }
 
+// The beta-gradient terms of a whole segment on states that are not rotated:
+// both states walk the layout chain and every register bit that is a qubit
+// of the group contributes its inner products.
+template <int L, bool FULL>
+__device__ inline float xb_round(const float2 (&ps)[REGS], const float2 (&la)[REGS], int c)
+{
+    float a = 0.f;
+    if (FULL || layout_bit0<L>() + 0 >= c) a += xb_bit<0>(ps, la);
+    if (FULL || layout_bit0<L>() + 1 >= c) a += xb_bit<1>(ps, la);
+    if (FULL || layout_bit0<L>() + 2 >= c) a += xb_bit<2>(ps, la);
+    if (FULL || layout_bit0<L>() + 3 >= c) a += xb_bit<3>(ps, la);
+    return a;
+}
+
+template <int CH, bool FULL, bool DIR>
+__device__ inline void seg_xb(float2 (&ps)[REGS], float2 (&la)[REGS], float2* lds, int c, uint32_t tid,
+                              double& xacc)
+{
+    constexpr int L0 = ChainAt<CH, DIR ? 0 : CH - 1>::L;
+    xacc += (double)xb_round<L0, FULL>(ps, la, c);
+    if constexpr (CH >= 2) {
+        constexpr int L1 = ChainAt<CH, DIR ? 1 : CH - 2>::L;
+        xchg<L0, L1>(lds, tid, ps);
+        xchg<L0, L1>(lds, tid, la);
+        xacc += (double)xb_round<L1, FULL>(ps, la, c);
+        if constexpr (CH >= 3) {
+            constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
+            xchg<L1, L2>(lds, tid, ps);
+            xchg<L1, L2>(lds, tid, la);
+            xacc += (double)xb_round<L2, FULL>(ps, la, c);
+        }
+    }
+}
+
 // C(z) for the 16 amplitudes a lane holds in layout L, for data permuted by
 // the flip mask m (slot q holds amplitude q ^ m). Group 0 reads the natural
 // table, the last group its tile-order copy (contiguous per tile).
@@ -730,11 +764,19 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_MF_W
 //         in memory already is the state before RX(pre)).
 // SINGLE: unmix(pre) with the beta-gradient; store both.
 // MID   : unmix(pre), gamma-gradient + unphase(ph), unmix(post); store both.
-// LAST  : unmix(pre), gamma-gradient; nothing stored.
+// LAST  : the inverse of the first forward pass (group 0 of layer 1): lambda
+//         is rotated back alone; psi at that point is the phased uniform
+//         state 2^(-n/2) e^{-i gamma_1 C(z)}, so it is synthesised from the cut
+//         table instead of read, and the beta terms of the segment are taken
+//         there (X_j commutes with every rotation of the layer, so the inner
+//         product <lambda|X_j|psi> is the same at any point of the layer);
+//         nothing stored.
+// STORE_PSI = false drops the psi store of the pass before LAST (LAST does
+// not read psi).
 // ---------------------------------------------------------------------------
 enum { B_FUSED = 0, B_SINGLE = 1, B_MID = 2, B_LAST = 3 };
 
-template <int CH, bool FULL, int KIND>
+template <int CH, bool FULL, int KIND, bool STORE_PSI = true>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_WAVES))) void k_bwd_pass(
     uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
 {
@@ -769,14 +811,35 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
             const float2 e = L[i];
             lut[i] = cmul(make_float2(e.x, -e.y), pre.Fi);
         }
+    } else if constexpr (KIND == B_LAST) {
+        // the phase table of layer 1 as the forward pass used it
+        const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
+        for (int i = tid; i < lut_len; i += THREADS) lut[i] = L[i];
     }
     float2 ps[REGS], la[REGS];
-    load_state<LS>(ps, sp, geo, tid);
+    if constexpr (KIND != B_LAST) load_state<LS>(ps, sp, geo, tid);
     if constexpr (KIND != B_FUSED) load_state<LS>(la, sl, geo, tid);
     __syncthreads();
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
     uint16_t cr[REGS];
-    if constexpr (KIND == B_FUSED) {
+    if constexpr (KIND == B_LAST) {
+        // lambda back through RX(pre); slot q then holds amplitude q ^ m_pre
+        seg_rot<CH, FULL, true>(la, lds, geo.c, -pre.t, tid);
+        scale_regs(la, pre.Fi);
+        load_cut_L<LE>(cr, tab, tid, m_pre);
+        const float amp = (float)(1.0 / sqrt((double)(1ull << sd->n)));
+        float a = 0.f;
+#pragma unroll
+        for (int r = 0; r < REGS; ++r) {
+            const float2 f = lut[cr[r]];
+            ps[r] = make_float2(amp * f.x, amp * f.y);
+            const float c = (float)cr[r];
+            a = fmaf(c * la[r].x, ps[r].y, a);
+            a = fmaf(-c * la[r].y, ps[r].x, a);
+        }
+        acc_ph = (double)a;
+        seg_xb<CH, FULL, false>(ps, la, lds, geo.c, tid, acc_pre);
+    } else if constexpr (KIND == B_FUSED) {
         // psi_p = RX(pre) psi (slot q then holds amplitude q ^ m_pre)
         seg_rot<CH, FULL, true>(ps, lds, geo.c, pre.t, tid);
         scale_regs(ps, pre.Ff);
@@ -825,10 +888,10 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     if constexpr (KIND == B_FUSED) {
         store_state<LS>(la, sl, geo, tid, 0u);
     } else if constexpr (KIND == B_SINGLE) {
-        store_state<LE>(ps, sp, geo, tid, m_end);
+        if constexpr (STORE_PSI) store_state<LE>(ps, sp, geo, tid, m_end);
         store_state<LE>(la, sl, geo, tid, m_end);
     } else if constexpr (KIND == B_MID) {
-        store_state<LS>(ps, sp, geo, tid, m_end);
+        if constexpr (STORE_PSI) store_state<LS>(ps, sp, geo, tid, m_end);
         store_state<LS>(la, sl, geo, tid, m_end);
     }
     // partial sums: (<C> or gamma, beta of pre, beta of post)
@@ -1023,6 +1086,17 @@ static size_t pass_lds(int lut_max) { return (size_t)(LDS_TILE + lut_max) * size
                                part);                                                                           \
     } while (0)
 
+#define PQ_LAUNCH_CH2(KERNEL, KIND, X)                                                                          \
+    do {                                                                                                        \
+        switch (chain) {                                                                                        \
+        case 3: hipLaunchKernelGGL((KERNEL<3, true, KIND, X>), g, b, lds, s, ws, subs, work, ops, part); break; \
+        case 2: hipLaunchKernelGGL((KERNEL<2, true, KIND, X>), g, b, lds, s, ws, subs, work, ops, part); break; \
+        case 4: hipLaunchKernelGGL((KERNEL<2, false, KIND, X>), g, b, lds, s, ws, subs, work, ops, part); break;\
+        case 1: hipLaunchKernelGGL((KERNEL<1, true, KIND, X>), g, b, lds, s, ws, subs, work, ops, part); break; \
+        default: hipLaunchKernelGGL((KERNEL<1, false, KIND, X>), g, b, lds, s, ws, subs, work, ops, part);      \
+        }                                                                                                       \
+    } while (0)
+
 hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain, PassOps ops,
                            Partials part, int lut_max, int prec, hipStream_t s)
 {
@@ -1049,9 +1123,13 @@ hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, i
     if (nwork <= 0) return hipSuccess;
     const size_t lds = pass_lds(lut_max);
     const dim3 g(nwork), b(THREADS);
+    // the last pass mirrors the first forward pass (group 0 of layer 1)
+    if (ops.last && (ops.group != 0 || chain != 3)) return hipErrorInvalidValue;
     if (ops.fused) PQ_LAUNCH_CH(k_bwd_pass, B_FUSED);
     else if (ops.last) PQ_LAUNCH_CH(k_bwd_pass, B_LAST);
+    else if (ops.ph >= 0 && ops.nopsi) PQ_LAUNCH_CH2(k_bwd_pass, B_MID, false);
     else if (ops.ph >= 0) PQ_LAUNCH_CH(k_bwd_pass, B_MID);
+    else if (ops.nopsi) PQ_LAUNCH_CH2(k_bwd_pass, B_SINGLE, false);
     else PQ_LAUNCH_CH(k_bwd_pass, B_SINGLE);
     return hipGetLastError();
 }
