@@ -36,8 +36,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "QAOA amp-updates/s + HBM GB/s; 2k-vertex solve time, learned vs plain angles"
-KERNELS = ["fwd_pass", "bwd_pass", "small", "cut_tables", "angle_prep", "reduce", "topk", "maxcut", "adam",
-           "merge"]
+PASSES = [f"fwd_{k}_g{g}" for k in ("first", "single", "mid", "last") for g in range(4)] + \
+    [f"bwd_{k}_g{g}" for k in ("fused", "single", "mid", "last", "single_nopsi", "mid_nopsi") for g in range(4)]
+KERNELS = PASSES + ["small", "cut_tables", "angle_prep", "reduce", "topk", "maxcut", "adam", "merge"]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -47,14 +48,17 @@ def log(*a):
 
 def traffic_record(kernel, workload):
     """Measured HBM traffic per launch of `kernel` from the committed PMC
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    summary of the workload, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_passes_{workload}.txt")
     if not os.path.exists(path):
         return None
     rec = None
     for line in open(path):
         if line.startswith("RECORD "):
-            rec = json.loads(line[len("RECORD "):])
+            r = json.loads(line[len("RECORD "):])
+            if r.get("kernel") == kernel:
+                rec = r
     if not rec:
         return None
     src = os.path.join(ROOT, "paper_2603_26232_amd", "csrc", rec.get("source", "sim.hip"))
@@ -253,7 +257,7 @@ def main():
         kern = read_profile()
         _abi.qaoa_profile_enable(0)
     dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else (
-        "fwd_pass" if args.workload == "precision26" else "bwd_pass")
+        "fwd_mid_g0" if args.workload == "precision26" else "bwd_mid_g0")
     if args.graph:
         log("bench: Adam steps replay a captured HIP graph")
     log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps (kernel events on {dom} only)")

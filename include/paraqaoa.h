@@ -275,14 +275,17 @@ const char* qaoa_last_error(void);
 
 /* Kernel timing for measurement: while enabled, the library brackets every
  * launch of its kernels with HIP events on the launch stream and adds up the
- * launch's algorithmic HBM bytes (each state read and written once per pass,
- * plus the uint16 cut table where the pass needs C(z)). qaoa_profile_read
- * waits for those events and returns, for the named kernel ("fwd_pass",
- * "bwd_pass", "small", "cut_tables", "angle_prep", "reduce", "topk",
- * "maxcut", "adam", "merge", "mlp_forward", "mlp_backward"), the number of
+ * launch's algorithmic HBM bytes (each state read and written once per pass
+ * where the pass needs it, plus the 1- or 2-byte cut table where the pass needs
+ * C(z)). qaoa_profile_read
+ * waits for those events and returns, for the named kernel, the number of
  * launches, their summed duration in milliseconds and their summed
- * algorithmic bytes since the last qaoa_profile_enable(1). Not for use while
- * another thread launches. */
+ * algorithmic bytes since the last qaoa_profile_enable(1). Names: the tile
+ * passes by direction, kind and qubit group, "fwd_{first,single,mid,last}_gG"
+ * and "bwd_{fused,single,mid,last,single_nopsi,mid_nopsi}_gG" (G = 0..3), and
+ * "small", "cut_tables", "angle_prep", "reduce", "topk", "maxcut", "adam",
+ * "merge", "mlp_forward", "mlp_backward". Not for use while another thread
+ * launches. */
 qaoa_status_t qaoa_profile_enable(int32_t on);
 /* Restrict the timing to one kernel name (NULL or "" = all). Each timed launch
  * adds two event records to its stream; timing only the kernel of interest

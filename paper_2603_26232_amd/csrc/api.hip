@@ -384,6 +384,28 @@ std::vector<PassOps> group_passes(const std::vector<Op>& ops)
 // Algorithmic HBM bytes of one tile pass: every state it touches read once
 // and written once (complex64, 8 B per amplitude) plus the uint16 cut table
 // when the pass needs C(z).
+// Profiling name of a pass kernel: direction, kind and qubit group (each is
+// its own kernel instantiation), e.g. "bwd_mid_g0".
+const char* pass_name(const PassOps& o, bool backward)
+{
+    static const char* const fk[] = {"first", "single", "mid", "last"};
+    static const char* const bk[] = {"fused", "single", "mid", "last", "single_nopsi", "mid_nopsi"};
+    static std::string names[2][6][MAX_GROUPS];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int g = 0; g < MAX_GROUPS; ++g) {
+            for (int k = 0; k < 4; ++k) names[0][k][g] = std::string("fwd_") + fk[k] + "_g" + std::to_string(g);
+            for (int k = 0; k < 6; ++k) names[1][k][g] = std::string("bwd_") + bk[k] + "_g" + std::to_string(g);
+        }
+    });
+    int k;
+    if (!backward) k = o.init ? 0 : o.epi_e ? 3 : o.ph >= 0 ? 2 : 1;
+    else if (o.fused) k = 0;
+    else if (o.last) k = 3;
+    else k = (o.ph >= 0 ? 2 : 1) + (o.nopsi ? 3 : 0);
+    return names[backward ? 1 : 0][k][o.group].c_str();
+}
+
 // algorithmic HBM bytes of one pass over a class: states read and written
 // once, the cut table (1 or 2 B per amplitude) where the pass needs C(z)
 double pass_bytes(const PassOps& o, bool backward, int nwork, double tab_bytes)
@@ -599,7 +621,7 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
             PassOps o = passes[i];
             o.init = i == 0;
             o.epi_e = i + 1 == passes.size();
-            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw, c.tab_bytes));
+            ProfScope ps(pass_name(o, false), st, pass_bytes(o, false, nw, c.tab_bytes));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, P.prec,
                                     st));
         }
@@ -666,7 +688,7 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         for (size_t i = 0; i + 1 < fwd.size(); ++i) {
             PassOps o = fwd[i];
             o.init = i == 0;
-            ProfScope ps("fwd_pass", st, pass_bytes(o, false, nw, c.tab_bytes));
+            ProfScope ps(pass_name(o, false), st, pass_bytes(o, false, nw, c.tab_bytes));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, 0, st));
         }
         std::vector<Op> rev(ops.rbegin(), ops.rend());
@@ -676,14 +698,14 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
         PassOps f = fwd.back();
         f.fused = 1;
         {
-            ProfScope ps("bwd_pass", st, pass_bytes(f, true, nw, c.tab_bytes));
+            ProfScope ps(pass_name(f, true), st, pass_bytes(f, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[f.group], f, h->part, P.lut_max, st));
         }
         for (size_t i = 1; i < bwd.size(); ++i) {
             PassOps o = bwd[i];
             o.last = i + 1 == bwd.size();
             o.nopsi = i + 2 == bwd.size();  // the last pass synthesises psi
-            ProfScope ps("bwd_pass", st, pass_bytes(o, true, nw, c.tab_bytes));
+            ProfScope ps(pass_name(o, true), st, pass_bytes(o, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }
     }
