@@ -69,20 +69,19 @@ __global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back,
                                const int64_t* ccut, const uint32_t* rows, int nw, const int64_t* scores,
                                const int32_t* npaths, uint64_t* keys)
 {
-    __shared__ int64_t A[32];
+    __shared__ int32_t A[32];
     const int p = blockIdx.x;
     if (p >= *npaths) return;
     const MergeLevel L = lv[i];
     const uint32_t* row = rows + (size_t)p * nw;
-    for (int k = threadIdx.x; k < 32; k += blockDim.x) {
-        int64_t a = 0;
-        if (k < L.size) {
-            for (int e = L.kbeg[k]; e < L.kbeg[k + 1]; ++e) {
-                const int32_t* E = back + 3 * (size_t)(L.back_off + e);
-                if (row_bit(row, E[0])) a += E[2];
-            }
-        }
-        A[k] = a;
+    if (threadIdx.x < 32) A[threadIdx.x] = 0;
+    __syncthreads();
+    // the level's back edges spread over the lanes (independent loads); the
+    // sums are integers (total weight < 2^31), so their order does not matter
+    const int nb = L.kbeg[32];
+    for (int e = threadIdx.x; e < nb; e += blockDim.x) {
+        const int32_t* E = back + 3 * (size_t)(L.back_off + e);
+        if (row_bit(row, E[0])) atomicAdd(&A[E[1]], E[2]);
     }
     __syncthreads();
     const int Kv = level_k(cand, K, i);
@@ -96,7 +95,7 @@ __global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back,
             int64_t s = ps + ccut[(size_t)i * K + j];
             for (int k = 1; k < L.size; ++k) {
                 const uint32_t y = ((b >> k) & 1u) ^ o;
-                s += y ? (L.wk[k] - A[k]) : A[k];
+                s += y ? (L.wk[k] - (int64_t)A[k]) : (int64_t)A[k];
             }
             const uint32_t order = (uint32_t)p * (uint32_t)K + (uint32_t)j;
             key = ((uint64_t)(s + 1) << 32) | (uint64_t)(0xFFFFFFFFu - order);
@@ -106,6 +105,7 @@ __global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back,
 }
 
 constexpr int SEL_THREADS = 1024;
+constexpr int SEL_BATCH = 8;
 constexpr int SEL_BINS = 4096;
 
 __device__ inline int64_t key_score(uint64_t k) { return (int64_t)(k >> 32) - 1; }
@@ -153,12 +153,22 @@ __global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* ke
     __syncthreads();
     int64_t best = INT64_MIN;
     int32_t valid = 0;
-    for (int64_t q = tid; q < N; q += SEL_THREADS) {
-        const uint64_t k = keys[q];
-        if (k) {
-            ++valid;
-            const int64_t sc = key_score(k);
-            best = sc > best ? sc : best;
+    // loads in batches of SEL_BATCH independent keys per thread (latency, not
+    // bandwidth, bounds a single workgroup)
+    for (int64_t q0 = tid; q0 < N; q0 += (int64_t)SEL_THREADS * SEL_BATCH) {
+        uint64_t kb[SEL_BATCH];
+#pragma unroll
+        for (int j = 0; j < SEL_BATCH; ++j) {
+            const int64_t q = q0 + (int64_t)j * SEL_THREADS;
+            kb[j] = q < N ? keys[q] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < SEL_BATCH; ++j) {
+            if (kb[j]) {
+                ++valid;
+                const int64_t sc = key_score(kb[j]);
+                best = sc > best ? sc : best;
+            }
         }
     }
     atomicAdd(&s_valid, valid);
@@ -179,11 +189,19 @@ __global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* ke
             for (int b = tid; b < SEL_BINS; b += SEL_THREADS) hist[b] = 0;
             if (tid == 0) s_found = 0;
             __syncthreads();
-            for (int64_t q = tid; q < N; q += SEL_THREADS) {
-                const uint64_t k = keys[q];
-                if (!k) continue;
-                const int64_t d = hi - key_score(k);
-                if (d >= 0 && d < SEL_BINS) atomicAdd(&hist[d], 1);
+            for (int64_t q0 = tid; q0 < N; q0 += (int64_t)SEL_THREADS * SEL_BATCH) {
+                uint64_t kb[SEL_BATCH];
+#pragma unroll
+                for (int j = 0; j < SEL_BATCH; ++j) {
+                    const int64_t q = q0 + (int64_t)j * SEL_THREADS;
+                    kb[j] = q < N ? keys[q] : 0ull;
+                }
+#pragma unroll
+                for (int j = 0; j < SEL_BATCH; ++j) {
+                    if (!kb[j]) continue;
+                    const int64_t d = hi - key_score(kb[j]);
+                    if (d >= 0 && d < SEL_BINS) atomicAdd(&hist[d], 1);
+                }
             }
             __syncthreads();
             // each thread owns 4 consecutive bins
@@ -225,12 +243,20 @@ __global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* ke
     const int64_t lo = (int64_t)wv * S, up = lo + S < N ? lo + S : N;
     const uint64_t below = (1ull << lane) - 1ull;
     int32_t gt = 0, eq = 0;
-    for (int64_t base = lo; base < up; base += 64) {
-        const int64_t q = base + lane;
-        const uint64_t k = q < up ? keys[q] : 0ull;
-        const int64_t sc = k ? key_score(k) : 0;
-        gt += __popcll(__ballot(k && sc > star));
-        eq += __popcll(__ballot(k && sc == star));
+    for (int64_t b0 = lo; b0 < up; b0 += 64 * SEL_BATCH) {
+        uint64_t kb[SEL_BATCH];
+#pragma unroll
+        for (int j = 0; j < SEL_BATCH; ++j) {
+            const int64_t q = b0 + 64 * j + lane;
+            kb[j] = q < up ? keys[q] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < SEL_BATCH; ++j) {
+            const uint64_t k = kb[j];
+            const int64_t sc = k ? key_score(k) : 0;
+            gt += __popcll(__ballot(k && sc > star));
+            eq += __popcll(__ballot(k && sc == star));
+        }
     }
     if (lane == 0) {
         wgt[wv] = gt;
@@ -242,23 +268,32 @@ __global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* ke
         gt_before += wgt[w];
         eq_before += weq[w];
     }
-    for (int64_t base = lo; base < up; base += 64) {
-        const int64_t q = base + lane;
-        const uint64_t k = q < up ? keys[q] : 0ull;
-        const int64_t sc = k ? key_score(k) : 0;
-        const bool g = k && sc > star, e = k && sc == star;
-        const uint64_t bg = __ballot(g), be = __ballot(e);
-        const int32_t my_gt = gt_before + __popcll(bg & below), my_eq = eq_before + __popcll(be & below);
-        if (g || (e && my_eq < R)) {
-            const int pos = my_gt + (my_eq < R ? my_eq : R);
-            Surv sv;
-            sv.parent = first ? 0 : (int32_t)(q / Kmul);
-            sv.digit = first ? (int32_t)q : (int32_t)(q % Kmul);
-            sv.score = sc;
-            surv[pos] = sv;
+    for (int64_t b0 = lo; b0 < up; b0 += 64 * SEL_BATCH) {
+        uint64_t kb[SEL_BATCH];
+#pragma unroll
+        for (int j = 0; j < SEL_BATCH; ++j) {
+            const int64_t q = b0 + 64 * j + lane;
+            kb[j] = q < up ? keys[q] : 0ull;
         }
-        gt_before += __popcll(bg);
-        eq_before += __popcll(be);
+#pragma unroll
+        for (int j = 0; j < SEL_BATCH; ++j) {
+            const int64_t q = b0 + 64 * j + lane;
+            const uint64_t k = kb[j];
+            const int64_t sc = k ? key_score(k) : 0;
+            const bool g = k && sc > star, e = k && sc == star;
+            const uint64_t bg = __ballot(g), be = __ballot(e);
+            const int32_t my_gt = gt_before + __popcll(bg & below), my_eq = eq_before + __popcll(be & below);
+            if (g || (e && my_eq < R)) {
+                const int pos = my_gt + (my_eq < R ? my_eq : R);
+                Surv sv;
+                sv.parent = first ? 0 : (int32_t)(q / Kmul);
+                sv.digit = first ? (int32_t)q : (int32_t)(q % Kmul);
+                sv.score = sc;
+                surv[pos] = sv;
+            }
+            gt_before += __popcll(bg);
+            eq_before += __popcll(be);
+        }
     }
     if (tid == 0) *nsurv = count;
 }

@@ -591,16 +591,46 @@ __global__ __launch_bounds__(THREADS) void k_cut_tables(uint8_t* ws, const SubDe
     const Geo geo = make_geo(sd, G >= 2 ? G - 1 : 0, t);
     uint8_t* tabB = ws + sd->tabB;
     const bool w1 = sd->tabw == 1;
-    for (uint32_t q = threadIdx.x; q < span; q += THREADS) {
-        const uint32_t z = t * TILE + q;
-        const uint32_t c = cut_of(z, E, ne);
-        if (w1) tab[z] = (uint8_t)c;
-        else ((uint16_t*)tab)[z] = (uint16_t)c;
-        if (G >= 2) {
-            const uint32_t cb = cut_of(geo.zb | gmap(geo, q), E, ne);
-            const size_t i = (size_t)t * TILE + q;
-            if (w1) tabB[i] = (uint8_t)cb;
-            else ((uint16_t*)tabB)[i] = (uint16_t)cb;
+    // four consecutive entries per thread, written as whole 32-bit words
+    // (span is 2^n or 4096; 2^n < 4 only for n = 1, handled entry by entry)
+    if (span >= 4) {
+        for (uint32_t q0 = 4 * threadIdx.x; q0 < span; q0 += 4 * THREADS) {
+            // one pass over the edges for all eight entries of the thread
+            uint32_t z[4], zB[4], c[4] = {0, 0, 0, 0}, cb[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                z[i] = t * TILE + q0 + i;
+                zB[i] = geo.zb | gmap(geo, q0 + i);
+            }
+            for (int e = 0; e < ne; ++e) {
+                const int32_t u = E[3 * e], v = E[3 * e + 1];
+                const uint32_t w = (uint32_t)E[3 * e + 2];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    c[i] += (((z[i] >> u) ^ (z[i] >> v)) & 1u) ? w : 0u;
+                    cb[i] += (((zB[i] >> u) ^ (zB[i] >> v)) & 1u) ? w : 0u;
+                }
+            }
+            const size_t z0 = (size_t)t * TILE + q0;
+            if (w1) {
+                *(uint32_t*)(tab + z0) = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+                if (G >= 2) *(uint32_t*)(tabB + z0) = cb[0] | (cb[1] << 8) | (cb[2] << 16) | (cb[3] << 24);
+            } else {
+                uint32_t* o = (uint32_t*)(tab + 2 * z0);
+                o[0] = c[0] | (c[1] << 16);
+                o[1] = c[2] | (c[3] << 16);
+                if (G >= 2) {
+                    uint32_t* ob = (uint32_t*)(tabB + 2 * z0);
+                    ob[0] = cb[0] | (cb[1] << 16);
+                    ob[1] = cb[2] | (cb[3] << 16);
+                }
+            }
+        }
+    } else {
+        for (uint32_t q = threadIdx.x; q < span; q += THREADS) {
+            const uint32_t c = cut_of(t * TILE + q, E, ne);
+            if (w1) tab[q] = (uint8_t)c;
+            else ((uint16_t*)tab)[q] = (uint16_t)c;
         }
     }
 }
