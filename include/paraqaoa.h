@@ -104,7 +104,8 @@ qaoa_status_t qaoa_workspace_bytes(int32_t B, const int32_t* num_qubits, const i
 
 /* Build a batch: validates the subgraphs, lays out states, cut tables, phase
  * tables and partial sums in the caller's workspace, copies the edge lists to
- * the device and builds every subgraph's integer cut table C(z) (uint16).
+ * the device and builds every subgraph's integer cut table C(z) (1 byte per
+ * entry when the subgraph's weight sum is at most 255, else 2).
  *   edge_u, edge_v host [off[B]] local vertex ids in [0, n_b), u != v
  *   edge_w         host weights >= 0 or NULL (unit); per-subgraph sum <= 2047
  *   d_workspace    device buffer of at least qaoa_workspace_bytes bytes,

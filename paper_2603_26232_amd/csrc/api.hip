@@ -381,9 +381,6 @@ std::vector<PassOps> group_passes(const std::vector<Op>& ops)
     return out;
 }
 
-// Algorithmic HBM bytes of one tile pass: every state it touches read once
-// and written once (complex64, 8 B per amplitude) plus the uint16 cut table
-// when the pass needs C(z).
 // Profiling name of a pass kernel: direction, kind and qubit group (each is
 // its own kernel instantiation), e.g. "bwd_mid_g0".
 const char* pass_name(const PassOps& o, bool backward)

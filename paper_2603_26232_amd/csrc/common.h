@@ -53,9 +53,10 @@ struct PassOps {
 };
 
 // Rotation parameters of one layer of one subgraph: e^{-i beta X} =
-// c (I - i t X) (mode 0, |cos| >= |sin|, t = tan beta) or -i s (X + i t I)
-// (mode 1, t = cot beta). Ff[g] / Fi[g] are the per-qubit factors raised to
-// the size of group g, forward (c or -i s) and inverse (c or +i s).
+// f (I - i t X) X^flip with (f, t) = (c, tan beta) (mode 0, |cos| >= |sin|,
+// no flip) or (-i s, -cot beta) (mode 1, flip). Ff[g] / Fi[g] are the
+// per-qubit factors raised to the size of group g, forward (c or -i s) and
+// inverse (c or +i s).
 struct RxCoef {
     float2 cs;  // (cos beta, sin beta)
     float t;

@@ -17,17 +17,20 @@
 // LDS. Consecutive layers visit the groups in alternating (serpentine) order,
 // so the last group of layer l and the first group of layer l+1 share one
 // HBM pass, with the diagonal phase of layer l+1 applied in registers from
-// a precomputed integer cut table C(z) (uint16) and an FP64-built phase
-// table e^{-i gamma c} rounded to complex64. <C> and the gradient inner
-// products are accumulated in FP64 per tile and reduced per subgraph in a
-// fixed order, so every result is bit-reproducible.
+// a precomputed integer cut table C(z) (1 byte per entry when the weight sum
+// is at most 255, else 2) and an FP64-built phase table e^{-i gamma c}
+// rounded to complex64. <C> and the gradient inner products are accumulated
+// in FP64 per tile and reduced per subgraph in a fixed order, so every result
+// is bit-reproducible.
 //
-// Rotation arithmetic: e^{-i beta X} = c (I - i t X) with t = tan beta when
-// |cos| >= |sin|, else -i s (X + i k I) with k = cot beta. The bracketed
-// operator costs two FMAs per real component; the per-qubit factor (c or
-// -i s) of a whole group is applied once per segment, folded into the next
-// phase multiply when there is one. Gradient inner products taken on scaled
-// states are rescaled by the known |factor|^2 powers.
+// Rotation arithmetic: e^{-i beta X} = f (I - i t X) X^flip with (f, t, flip)
+// = (cos beta, tan beta, 0) when |cos| >= |sin|, else (-i sin beta,
+// -cot beta, 1), so |t| <= 1. The bracketed operator costs two FMAs per real
+// component; the per-qubit factor f of a whole group is applied once per
+// segment, folded into the next phase multiply when there is one; the X^flip
+// permutation is never executed but carried as an XOR mask on tile positions
+// into cut-table reads and store addresses. Gradient inner products taken on
+// scaled states are rescaled by the known |f|^2 powers.
 #include "common.h"
 
 // Occupancy targets of the tile passes (waves per SIMD): the register budget
