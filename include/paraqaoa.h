@@ -251,21 +251,26 @@ qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_t hidden, i
                                 double* d_loss, qaoa_stream_t stream);
 
 /* Where subgraph b's state lives: the byte offset, inside the workspace, of
- * its 2^n complex64 amplitudes (interleaved real, imaginary; index z). After
- * qaoa_apply_layers they hold |psi>; after qaoa_expectation_grad they hold
- * an intermediate of the adjoint sweep. For inspection and tests. */
+ * its stored amplitudes. The ansatz state is invariant under flipping every
+ * bit (H_C, H_M and |+>^n all commute with X on every qubit, Sec. 2.2), so
+ * only the 2^(n-1) amplitudes phi(z) = sqrt(2) psi(z), z < 2^(n-1), are stored
+ * (complex64, interleaved real, imaginary); psi(z) = phi(z) / sqrt(2) and
+ * psi(z) = psi(z XOR (2^n - 1)) for the upper half. After qaoa_apply_layers
+ * they hold |psi>; after qaoa_expectation_grad an intermediate of the adjoint
+ * sweep. For inspection and tests. */
 qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* out_offset);
 
 /* Tuning of the strided qubit groups (process-wide, read when a batch is
- * created). Subgraphs with n > 12 qubits split them into group 0 (qubits
- * 0..11, contiguous tiles) and strided groups of at most 8 qubits, one HBM pass
- * per group and layer (Sec. 2.2's mixer is a product over qubits, so any
- * grouping gives the same state). sizes[0..count) are the strided group sizes
- * in qubit order for subgraphs with n qubits (each 1..8, at most 3 groups,
- * adding up to n - 12); count = 0 restores the default (fewest groups, sizes
- * as even as possible). Batches created earlier keep their layout.
- * QAOA_ERR_OUT_OF_RANGE for n outside 13..30, count > 3 or a size outside
- * 1..8; QAOA_ERR_INVALID_ARG if the sizes do not add up to n - 12. */
+ * created). Subgraphs with n > 13 qubits are simulated in group 0 (qubits
+ * 0..10 and the top qubit, 4096-amplitude tiles) and strided groups of at most
+ * 8 of the qubits 11..n-2, one HBM pass per group and layer (Sec. 2.2's mixer
+ * is a product over qubits, so any grouping gives the same state).
+ * sizes[0..count) are the strided group sizes in qubit order for subgraphs
+ * with n qubits (each 1..8, at most 3 groups, adding up to n - 12); count = 0
+ * restores the default (fewest groups, sizes as even as possible). Batches
+ * created earlier keep their layout. QAOA_ERR_OUT_OF_RANGE for n outside
+ * 14..30, count > 3 or a size outside 1..8; QAOA_ERR_INVALID_ARG if the sizes
+ * do not add up to n - 12. */
 qaoa_status_t qaoa_tune_group_split(int32_t n, int32_t count, const int32_t* sizes);
 
 /* Text of a status code (static storage). */

@@ -1,11 +1,12 @@
 """Autotuner for the strided qubit groups of the tile passes.
 
-A subgraph with n > 12 qubits is simulated in group 0 (qubits 0..11,
-contiguous 4096-amplitude tiles) plus strided groups of at most 8 qubits, one
-HBM pass per group and layer. How the n - 12 strided qubits are split decides
-each pass's register layout chain, how many register bits are real qubits and
-how long the contiguous rows of a strided tile are (2^(12 - size)
-amplitudes). Every split gives the same state; the tuner times the
+A subgraph with n > 13 qubits is simulated in group 0 (qubits 0..10 and the
+top qubit, which acts on the stored half-state as the complement; 4096-
+amplitude tiles of two mirrored blocks) plus strided groups of at most 8 of
+the qubits 11..n-2, one HBM pass per group and layer. How the n - 12 strided
+qubits are split decides each pass's register layout chain, how many register
+bits are real qubits and how long the contiguous rows of a strided tile are
+(2^(12 - size) amplitudes). Every split gives the same state; the tuner times the
 candidate splits (fewest groups, every ordered composition of n - 12 into
 parts of at most 8) on a batch of random graphs with n qubits, one optimiser
 evaluation (forward pass + adjoint sweep) or one forward evaluation per
@@ -33,7 +34,7 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 def candidates(n: int, max_parts: int = 3):
     """Ordered compositions of n - 12 into the fewest parts of size 1..8."""
     R = n - 12
-    if R <= 0:
+    if n <= 13:  # whole-state kernel, no strided groups
         return []
     parts = -(-R // 8)
     if parts > max_parts:
@@ -121,7 +122,7 @@ def apply(path: str = DEFAULT_TABLE) -> dict:
     return out
 
 
-def reset(ns=range(13, 31)):
+def reset(ns=range(14, 31)):
     for n in ns:
         _abi.qaoa_tune_group_split(n, None)
 

@@ -85,11 +85,19 @@ class QaoaBatch:
                                    _stream(stream))
         return E, dg.view(self.B, p), db.view(self.B, p)
 
-    def state(self, b: int) -> torch.Tensor:
-        """View of subgraph b's complex64 state inside the workspace."""
+    def reduced_state(self, b: int) -> torch.Tensor:
+        """View of subgraph b's stored state inside the workspace: the 2^(n-1)
+        amplitudes with the top bit clear, scaled by sqrt(2) (unit norm)."""
         off = _abi.qaoa_state_offset(self.handle, b)
         n = int(self.sizes[b])
-        return self.workspace[off:off + 8 * (1 << n)].view(torch.complex64)
+        return self.workspace[off:off + 8 * (1 << (n - 1))].view(torch.complex64)
+
+    def state(self, b: int) -> torch.Tensor:
+        """Subgraph b's full complex64 state (a new tensor): psi(z) =
+        phi(z) / sqrt(2) for z < 2^(n-1), and psi(z) = psi(complement of z),
+        i.e. the upper half is the lower half reversed."""
+        phi = self.reduced_state(b)
+        return torch.cat([phi, phi.flip(0)]) * (2.0 ** -0.5)
 
 
 def idx_to_uint32(idx: torch.Tensor) -> np.ndarray:

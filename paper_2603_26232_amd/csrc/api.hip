@@ -233,11 +233,13 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
                         QAOA_MAX_WEIGHT_SUM);
         SubDesc& d = P.subs[b];
         d.n = n;
+        // group 0: qubits 0..10 and the top qubit (the complement of a reduced
+        // index, tile bit 11); strided groups: qubits 11..n-2 of the reduced index
         d.gstart[0] = 0;
-        d.gsize[0] = n < TILE_BITS ? n : TILE_BITS;
+        d.gsize[0] = n <= SMALL_MAX_N ? n : TILE_BITS;
         d.ngroups = 1;
         if (n > SMALL_MAX_N) {
-            int q = TILE_BITS;
+            int q = HALF_BITS;
             for (int sz : group_split(n)) {
                 d.gstart[d.ngroups] = q;
                 d.gsize[d.ngroups] = sz;
@@ -248,7 +250,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
         d.lut_len = (int32_t)wsum + 1;
         d.tabw = wsum <= 255 ? 1 : 2;
         d.skip = (flags & QAOA_FLAG_SKIP_EDGELESS) && eoff[b + 1] == eoff[b];
-        d.ntiles = d.skip ? 0 : (n > TILE_BITS ? (1 << (n - TILE_BITS)) : 1);
+        d.ntiles = d.skip ? 0 : (n > SMALL_MAX_N ? (1 << (n - 1 - TILE_BITS)) : 1);
         d.tile_base = (int32_t)tiles;
         d.nedges = (int32_t)(eoff[b + 1] - eoff[b]);
         tiles += d.ntiles;
@@ -316,7 +318,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     uint64_t lut_o = P.o_lut, eo = P.o_edges;
     for (int b = 0; b < B; ++b) {
         SubDesc& d = P.subs[b];
-        const uint64_t dim = 1ull << d.n;
+        const uint64_t dim = 1ull << (d.n - 1);  // reduced state
         d.coef = P.o_coef + sizeof(RxCoef) * (uint64_t)b * max_p;
         d.lut = lut_o;
         lut_o += sizeof(float2) * (uint64_t)max_p * d.lut_len;
@@ -439,7 +441,8 @@ double small_bytes(const Plan& P, int p, bool grad)
 {
     double b = 0.0;
     for (const SubDesc& d : P.subs)
-        if (d.ngroups == 1 && !d.skip) b += (double)(1ull << d.n) * (grad ? d.tabw * (2.0 * p + 2) : (d.tabw * (p + 1.0) + 8.0));
+        if (d.ngroups == 1 && !d.skip)
+            b += (double)(1ull << (d.n - 1)) * (grad ? d.tabw * (2.0 * p + 2) : (d.tabw * (p + 1.0) + 8.0));
     return b;
 }
 
@@ -568,7 +571,7 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
     {
         double tb = 0.0;
         for (const SubDesc& d : h->P.subs)
-            if (!d.skip) tb += (double)(1ull << d.n) * (d.ngroups >= 2 ? 4.0 : 2.0);
+            if (!d.skip) tb += (double)(1ull << (d.n - 1)) * d.tabw * (d.ngroups >= 2 ? 2.0 : 1.0);
         ProfScope ps("cut_tables", st, tb);
         hipError_t e = launch_cut_tables(ws, h->d_subs, (const int2*)(ws + h->P.o_work_all), h->P.total_tiles, st);
         if (e != hipSuccess) {
@@ -649,7 +652,7 @@ extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, f
     const Plan& P = h->P;
     double tk = 0.0;
     for (const SubDesc& d : P.subs)
-        if (!d.skip) tk += (double)(1ull << d.n) * 8.0;
+        if (!d.skip) tk += (double)(1ull << (d.n - 1)) * 8.0;
     ProfScope ps("topk", st, tk + 16.0 * P.total_tiles * k);
     HIP_TRY(launch_topk(h->ws, h->d_subs, (const int2*)(h->ws + P.o_work_all), P.total_tiles, P.B, k,
                         (P.flags & QAOA_FLAG_TOPK_RAW) ? 0 : 1, (uint64_t*)(h->ws + P.o_keys), d_idx, d_prob,

@@ -21,7 +21,11 @@ constexpr int MAX_GROUPS = 4;  // qubit groups per subgraph (n <= 30)
 constexpr int MAX_P = 32;      // QAOA depth limit
 constexpr int MAX_K = 64;      // top-k limit
 constexpr int LUT_MAX = 2048;  // phase table entries per layer (sum of weights + 1)
-constexpr int SMALL_MAX_N = 12;  // n <= 12: the whole state is one workgroup's tile
+// Stored states are symmetry-reduced: the ansatz state is invariant under
+// flipping every bit (psi(~z) = psi(z)), so only the 2^(n-1) amplitudes with
+// the top bit clear are stored, scaled by sqrt(2) to unit norm.
+constexpr int HALF_BITS = TILE_BITS - 1;  // qubits 0..10 in group 0; tile bit 11 = the complement
+constexpr int SMALL_MAX_N = 13;  // n <= 13: the reduced state (<= 4096 amplitudes) is one workgroup's tile
 constexpr int B_GROUP_MAX = 8;   // active qubits of a strided (high) group
 
 // Per-subgraph descriptor, resident in the workspace.

@@ -7,11 +7,15 @@
 // <C>_b = sum_z |psi_b(z)|^2 C_b(z) and, for the angle optimiser, the exact
 // gradient by the adjoint sweep.
 //
-// How (MI355X design): the state of one subgraph (complex64, 2^n amplitudes)
-// is processed in tiles of 2^12 amplitudes. Qubits are split into groups:
-// group 0 = qubits 0..11 (a tile is 4096 contiguous amplitudes), groups 1..
-// = up to 8 higher qubits each (a tile is 2^(12-nb) contiguous amplitudes
-// times 2^nb strided rows). A workgroup keeps its tile in registers (16
+// How (MI355X design): the state is invariant under flipping every bit
+// (C(~z) = C(z); X on every qubit commutes with both operators and fixes
+// |+>), so only the 2^(n-1) amplitudes with the top bit clear are stored,
+// scaled by sqrt(2); on them the top qubit's X maps an index to its
+// complement. The stored state is processed in tiles of 2^12 amplitudes.
+// Qubits are split into groups: group 0 = qubits 0..10 plus the top qubit (a
+// tile is a block of 2048 contiguous amplitudes and its mirror block, tile
+// bit 11 choosing between them), groups 1.. = up to 8 of the qubits 11..n-2
+// each (a tile is 2^(12-nb) contiguous amplitudes times 2^nb strided rows). A workgroup keeps its tile in registers (16
 // amplitudes per lane) and applies the rotations of 4 register-resident
 // qubits at a time; between rounds the tile changes register layout through
 // LDS. Consecutive layers visit the groups in alternating (serpentine) order,
@@ -51,16 +55,34 @@ namespace pq {
 // tile geometry
 // ---------------------------------------------------------------------------
 struct Geo {
-    uint32_t zb;  // fixed z bits of this tile
-    int c;        // passive low tile bits (contiguous amplitudes)
-    int g0;       // first qubit of the group
-    int nb;       // qubits in the group (active tile bits = [c, 12))
+    uint32_t zb;   // fixed index bits of this tile
+    int c;         // passive low tile bits (contiguous amplitudes)
+    int g0;        // first qubit of the group
+    int nb;        // qubits in the group (active tile bits = [c, 12))
+    uint32_t mir;  // group 0: 2^(n-1) - 1 (the complement of a reduced index)
 };
 
 // tile position q -> z offset (bit deposit; zb supplies the fixed bits)
 __device__ inline uint32_t gmap(const Geo& g, uint32_t q)
 {
     return (q & ((1u << g.c) - 1u)) | ((q >> g.c) << g.g0);
+}
+
+// Group 0 tiles pair a block of 2048 reduced indices with its mirror block:
+// tile bits 0..10 are qubits 0..10 and tile bit 11 selects the block or its
+// complement (index XOR 2^(n-1) - 1). In the reduced state the top qubit's
+// X maps an index to its complement, so it acts on tile bit 11 like any other
+// qubit on its bit. The map is XOR-linear, as the deposit of the other groups.
+__device__ inline uint32_t gmap0(const Geo& g, uint32_t q)
+{
+    return (q & ((1u << HALF_BITS) - 1u)) ^ ((q >> HALF_BITS) & 1u ? g.mir : 0u);
+}
+
+template <bool G0>
+__device__ inline uint32_t gmapT(const Geo& g, uint32_t q)
+{
+    if constexpr (G0) return gmap0(g, q);
+    else return gmap(g, q);
 }
 
 // Register layouts of a 4096-amplitude tile over 256 lanes x 16 registers.
@@ -477,32 +499,33 @@ __device__ inline void load_cut_L(uint16_t (&cr)[REGS], const CutTab& tab, uint3
     }
 }
 
-// the tile's slice of the table: natural order for group 0, the tile-ordered
-// copy for the last group
+// the tile's slice of the table: both tables are stored in tile order (group
+// 0's mirror-paired tiles and the last group's strided tiles)
 __device__ inline CutTab tile_tab(const uint8_t* ws, const SubDesc* sd, int g, const Geo& geo, uint32_t t)
 {
     const int w = sd->tabw;
-    return CutTab{g == 0 ? ws + sd->tab + (size_t)geo.zb * w : ws + sd->tabB + (size_t)t * TILE * w, w};
+    (void)geo;
+    return CutTab{(g == 0 ? ws + sd->tab : ws + sd->tabB) + (size_t)t * TILE * w, w};
 }
 
-template <int L>
+template <int L, bool G0>
 __device__ inline void load_state(float2 (&v)[REGS], const float2* st, const Geo& geo, uint32_t tid)
 {
-    const float2* p = st + (geo.zb | gmap(geo, thread_part<L>(tid)));
+    const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid));
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) v[r] = p[gmap(geo, reg_part<L>(r))];
+    for (int r = 0; r < REGS; ++r) v[r] = st[base ^ gmapT<G0>(geo, reg_part<L>(r))];
     __builtin_amdgcn_sched_barrier(0);
 }
 
 // store slot q to amplitude q ^ m (gmap is a bit deposit, so it commutes with xor)
-template <int L>
+template <int L, bool G0>
 __device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Geo& geo, uint32_t tid, uint32_t m)
 {
     // address arithmetic stays here (hoisting it holds 2 VGPRs per register)
     __builtin_amdgcn_sched_barrier(0);
-    const uint32_t base = (geo.zb | gmap(geo, thread_part<L>(tid))) ^ gmap(geo, m);
+    const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid)) ^ gmapT<G0>(geo, m);
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) st[base ^ gmap(geo, reg_part<L>(r))] = v[r];
+    for (int r = 0; r < REGS; ++r) st[base ^ gmapT<G0>(geo, reg_part<L>(r))] = v[r];
 }
 
 // deterministic block sum (wave64 butterfly, then the 4 wave totals in order)
@@ -562,11 +585,13 @@ __device__ inline uint32_t cut_of(uint32_t z, const int32_t* E, int ne)
 __device__ inline Geo make_geo(const SubDesc* sd, int g, uint32_t t)
 {
     Geo r;
+    r.mir = 0;
     if (g == 0) {
         r.c = 0;
         r.g0 = 0;
         r.nb = TILE_BITS;
-        r.zb = t << TILE_BITS;
+        r.zb = t << HALF_BITS;
+        r.mir = (1u << (sd->n - 1)) - 1u;
     } else {
         r.nb = sd->gsize[g];
         r.g0 = sd->gstart[g];
@@ -583,27 +608,31 @@ __device__ inline Geo make_geo(const SubDesc* sd, int g, uint32_t t)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(THREADS) void k_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work)
 {
+    // C(z) of the reduced indices (top bit clear: C of the full index is the
+    // same). Whole-state subgraphs: natural order; tiled ones: group 0's
+    // mirror-paired tile order in tab, the last group's tile order in tabB.
     const int2 wk = work[blockIdx.x];
     const SubDesc* sd = subs + wk.x;
     const uint32_t t = (uint32_t)wk.y;
     const int n = sd->n, ne = sd->nedges, G = sd->ngroups;
     const int32_t* E = (const int32_t*)(ws + sd->edges);
     uint8_t* tab = ws + sd->tab;
-    const uint32_t dim = 1u << n;
+    const uint32_t dim = 1u << (n - 1);
     const uint32_t span = dim < (uint32_t)TILE ? dim : (uint32_t)TILE;
-    const Geo geo = make_geo(sd, G >= 2 ? G - 1 : 0, t);
+    const Geo geoA = make_geo(sd, 0, t);
+    const Geo geoB = make_geo(sd, G >= 2 ? G - 1 : 0, t);
     uint8_t* tabB = ws + sd->tabB;
     const bool w1 = sd->tabw == 1;
     // four consecutive entries per thread, written as whole 32-bit words
-    // (span is 2^n or 4096; 2^n < 4 only for n = 1, handled entry by entry)
+    // (span is 2^(n-1) or 4096; below 4 only for n <= 2, entry by entry)
     if (span >= 4) {
         for (uint32_t q0 = 4 * threadIdx.x; q0 < span; q0 += 4 * THREADS) {
             // one pass over the edges for all eight entries of the thread
             uint32_t z[4], zB[4], c[4] = {0, 0, 0, 0}, cb[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                z[i] = t * TILE + q0 + i;
-                zB[i] = geo.zb | gmap(geo, q0 + i);
+                z[i] = G >= 2 ? geoA.zb ^ gmap0(geoA, q0 + i) : q0 + i;
+                zB[i] = geoB.zb | gmap(geoB, q0 + i);
             }
             for (int e = 0; e < ne; ++e) {
                 const int32_t u = E[3 * e], v = E[3 * e + 1];
@@ -631,7 +660,7 @@ __global__ __launch_bounds__(THREADS) void k_cut_tables(uint8_t* ws, const SubDe
         }
     } else {
         for (uint32_t q = threadIdx.x; q < span; q += THREADS) {
-            const uint32_t c = cut_of(t * TILE + q, E, ne);
+            const uint32_t c = cut_of(q, E, ne);
             if (w1) tab[q] = (uint8_t)c;
             else ((uint16_t*)tab)[q] = (uint16_t)c;
         }
@@ -741,11 +770,11 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     if constexpr (KIND == F_LAST) load_cut_L<LE>(cr, tab, tid, m_end);
     float2 v[REGS];
     if constexpr (KIND == F_FIRST) {
-        const float a = (float)(1.0 / sqrt((double)(1ull << sd->n)));
+        const float a = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
 #pragma unroll
         for (int r = 0; r < REGS; ++r) v[r] = make_float2(a, 0.f);
     } else {
-        load_state<LS>(v, st, geo, tid);
+        load_state<LS, CH == 3>(v, st, geo, tid);
     }
     __syncthreads();  // phase table staged
     if constexpr (HAS_PRE) {
@@ -767,8 +796,8 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     }
     // after one segment the layout is the chain end; after two it is back at
     // the start (stores first: they drain while the partial sum is reduced)
-    if constexpr (KIND == F_MID) store_state<LS>(v, st, geo, tid, m_end);
-    else store_state<LE>(v, st, geo, tid, m_end);
+    if constexpr (KIND == F_MID) store_state<LS, CH == 3>(v, st, geo, tid, m_end);
+    else store_state<LE, CH == 3>(v, st, geo, tid, m_end);
     if constexpr (KIND == F_LAST) {
         acc = block_sum(acc, red);
         if (tid == 0) part.e[sd->tile_base + t] = acc;
@@ -799,7 +828,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_MF_W
 // MID   : unmix(pre), gamma-gradient + unphase(ph), unmix(post); store both.
 // LAST  : the inverse of the first forward pass (group 0 of layer 1): lambda
 //         is rotated back alone; psi at that point is the phased uniform
-//         state 2^(-n/2) e^{-i gamma_1 C(z)}, so it is synthesised from the cut
+//         state (stored half: 2^(-(n-1)/2) e^{-i gamma_1 C(z)}), so it is
+//         synthesised from the cut
 //         table instead of read, and the beta terms of the segment are taken
 //         there (X_j commutes with every rotation of the layer, so the inner
 //         product <lambda|X_j|psi> is the same at any point of the layer);
@@ -850,8 +880,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
         for (int i = tid; i < lut_len; i += THREADS) lut[i] = L[i];
     }
     float2 ps[REGS], la[REGS];
-    if constexpr (KIND != B_LAST) load_state<LS>(ps, sp, geo, tid);
-    if constexpr (KIND != B_FUSED) load_state<LS>(la, sl, geo, tid);
+    if constexpr (KIND != B_LAST) load_state<LS, CH == 3>(ps, sp, geo, tid);
+    if constexpr (KIND != B_FUSED) load_state<LS, CH == 3>(la, sl, geo, tid);
     __syncthreads();
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
     uint16_t cr[REGS];
@@ -860,7 +890,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
         seg_rot<CH, FULL, true>(la, lds, geo.c, -pre.t, tid);
         scale_regs(la, pre.Fi);
         load_cut_L<LE>(cr, tab, tid, m_pre);
-        const float amp = (float)(1.0 / sqrt((double)(1ull << sd->n)));
+        const float amp = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
         float a = 0.f;
 #pragma unroll
         for (int r = 0; r < REGS; ++r) {
@@ -919,13 +949,13 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
     }
     // results first (the stores drain while the partial sums are reduced)
     if constexpr (KIND == B_FUSED) {
-        store_state<LS>(la, sl, geo, tid, 0u);
+        store_state<LS, CH == 3>(la, sl, geo, tid, 0u);
     } else if constexpr (KIND == B_SINGLE) {
-        if constexpr (STORE_PSI) store_state<LE>(ps, sp, geo, tid, m_end);
-        store_state<LE>(la, sl, geo, tid, m_end);
+        if constexpr (STORE_PSI) store_state<LE, CH == 3>(ps, sp, geo, tid, m_end);
+        store_state<LE, CH == 3>(la, sl, geo, tid, m_end);
     } else if constexpr (KIND == B_MID) {
-        if constexpr (STORE_PSI) store_state<LS>(ps, sp, geo, tid, m_end);
-        store_state<LS>(la, sl, geo, tid, m_end);
+        if constexpr (STORE_PSI) store_state<LS, CH == 3>(ps, sp, geo, tid, m_end);
+        store_state<LS, CH == 3>(la, sl, geo, tid, m_end);
     }
     // partial sums: (<C> or gamma, beta of pre, beta of post)
     double s0 = KIND == B_FUSED ? acc_e : acc_ph, s1 = acc_pre, s2 = acc_post;
@@ -959,7 +989,10 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
     const uint32_t tid = threadIdx.x;
     const SubDesc* sd = subs + list[blockIdx.x];
     const int n = sd->n;
-    const uint32_t dim = 1u << n, half = dim >> 1;
+    // the reduced state: qubits 0..n-2 act on the index bits, the top qubit's
+    // X on an index pairs it with its complement (dim - 1 - index); for n = 1
+    // that pair is the single amplitude itself
+    const uint32_t dim = 1u << (n - 1), half = dim >> 1, comp = dim - 1;
     float2* ps = smem;
     float2* la = smem + TILE;
     float2* lut = smem + (grad ? 2 * TILE : TILE);
@@ -978,13 +1011,16 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
         __syncthreads();
         for (uint32_t z = tid; z < dim; z += THREADS) ps[z] = cmul(ps[z], lut[tab.at(z)]);
         const float2 cs = cf[l].cs;
-        for (int j = 0; j < n; ++j) {
+        for (int j = 0; j < n - 1; ++j) {
             __syncthreads();
             for (uint32_t i = tid; i < half; i += THREADS) {
                 const uint32_t z = ((i >> j) << (j + 1)) | (i & ((1u << j) - 1u));
                 rx_pair(ps[z], ps[z | (1u << j)], cs.x, cs.y);
             }
         }
+        __syncthreads();
+        for (uint32_t i = tid; i < half; i += THREADS) rx_pair(ps[i], ps[i ^ comp], cs.x, cs.y);
+        if (dim == 1 && tid == 0) ps[0] = cmul(ps[0], make_float2(cs.x, -cs.y));
     }
     __syncthreads();
     double acc = 0.0;
@@ -1004,16 +1040,25 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
     for (int l = p - 1; l >= 0; --l) {
         const float2 cs = cf[l].cs;
         double xb = 0.0;
-        for (int j = 0; j < n; ++j) {
+        // the top qubit (complement pairs) first, then qubits n-2..0
+        for (int j = n - 1; j >= 0; --j) {
             __syncthreads();
             float a = 0.f;
-            for (uint32_t i = tid; i < half; i += THREADS) {
-                const uint32_t z = ((i >> j) << (j + 1)) | (i & ((1u << j) - 1u));
-                const uint32_t z1 = z | (1u << j);
-                a += la[z].x * ps[z1].y - la[z].y * ps[z1].x;
-                a += la[z1].x * ps[z].y - la[z1].y * ps[z].x;
-                rx_pair(ps[z], ps[z1], cs.x, -cs.y);
-                rx_pair(la[z], la[z1], cs.x, -cs.y);
+            if (j == n - 1 && dim == 1) {
+                if (tid == 0) {
+                    a += la[0].x * ps[0].y - la[0].y * ps[0].x;
+                    ps[0] = cmul(ps[0], make_float2(cs.x, cs.y));
+                    la[0] = cmul(la[0], make_float2(cs.x, cs.y));
+                }
+            } else {
+                for (uint32_t i = tid; i < half; i += THREADS) {
+                    const uint32_t z = j == n - 1 ? i : ((i >> j) << (j + 1)) | (i & ((1u << j) - 1u));
+                    const uint32_t z1 = j == n - 1 ? i ^ comp : z | (1u << j);
+                    a += la[z].x * ps[z1].y - la[z].y * ps[z1].x;
+                    a += la[z1].x * ps[z].y - la[z1].y * ps[z].x;
+                    rx_pair(ps[z], ps[z1], cs.x, -cs.y);
+                    rx_pair(la[z], la[z1], cs.x, -cs.y);
+                }
             }
             xb += (double)a;
         }

@@ -10,9 +10,10 @@
 // Both stages find the k largest keys of a set by a most-significant-digit
 // radix select in LDS (8-bit digits, one histogram per digit, stopping as
 // soon as every key that shares the current prefix is needed), instead of
-// sorting: stage 1 takes one 4096-amplitude tile per block, with its
-// candidates in registers, and writes the tile's best k unsorted; stage 2
-// selects a subgraph's best k from its per-tile lists and sorts only those.
+// sorting: stage 1 takes one 4096-amplitude tile of the reduced state per
+// block, with its candidates in registers, and writes the tile's best k
+// unsorted; stage 2 selects a subgraph's best k from its per-tile lists and
+// sorts only those.
 // Canonical mode takes only z with bit 0 clear (pi(z) = pi(~z)).
 #include "common.h"
 
@@ -90,9 +91,8 @@ __device__ inline bool selected(uint64_t key, uint64_t prefix, int digits)
     return digits == 0 || (key >> (64 - 8 * digits)) >= prefix;
 }
 
-__device__ inline uint64_t make_key(float2 a, uint32_t z)
+__device__ inline uint64_t make_key(float pr, uint32_t z)
 {
-    const float pr = a.x * a.x + a.y * a.y;
     return ((uint64_t)__float_as_uint(pr) << 32) | (uint64_t)(0xFFFFFFFFu - z);
 }
 
@@ -101,31 +101,38 @@ template <bool CANON>
 __global__ __launch_bounds__(THREADS) void k_topk_tile(const uint8_t* ws, const SubDesc* subs, const int2* work,
                                                       int k, uint64_t* out)
 {
-    constexpr int PER = CANON ? 8 : 16;  // candidates per thread (4096 / 256 / step)
+    // The stored state is reduced: amplitude z' (top bit clear, scaled by
+    // sqrt(2)) stands for z' and its complement z' ^ (2^n - 1), each with
+    // probability |phi(z')|^2 / 2. The canonical one of the pair is the one
+    // with bit 0 clear; raw mode takes both.
+    constexpr int AMPS = TILE / THREADS;          // 16 amplitudes per thread
+    constexpr int PER = CANON ? AMPS : 2 * AMPS;  // candidates per thread
     __shared__ SelState S;
     const int2 wk = work[blockIdx.x];
     const SubDesc* d = subs + wk.x;
     const int n = d->n;
     const uint32_t base = (uint32_t)wk.y * TILE;
-    const float4* st = (const float4*)(ws + d->psi) + base / 2;
-    const uint32_t span = n < TILE_BITS ? (1u << n) : (uint32_t)TILE;
-    const uint32_t npair = span / 2;  // float4 = amplitudes (2c, 2c + 1)
+    const float2* st = (const float2*)(ws + d->psi) + base;
+    const uint32_t span = n - 1 < TILE_BITS ? (1u << (n - 1)) : (uint32_t)TILE;
+    const uint32_t full = (uint32_t)((1ull << n) - 1ull);
     const int t = threadIdx.x;
     uint64_t key[PER];
 #pragma unroll
-    for (int j = 0; j < (CANON ? PER : PER / 2); ++j) {
+    for (int j = 0; j < AMPS; ++j) {
         const uint32_t c = (uint32_t)t + (uint32_t)j * THREADS;
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-        const bool ok = c < npair;
+        const bool ok = c < span;
+        float2 a = make_float2(0.f, 0.f);
         if (ok) a = st[c];
+        const float pr = 0.5f * (a.x * a.x + a.y * a.y);
+        const uint32_t z = base + c;
         if (CANON) {
-            key[j] = ok ? make_key(make_float2(a.x, a.y), base + 2 * c) : 0ull;
+            key[j] = ok ? make_key(pr, (z & 1u) ? z ^ full : z) : 0ull;
         } else {
-            key[2 * j] = ok ? make_key(make_float2(a.x, a.y), base + 2 * c) : 0ull;
-            key[2 * j + 1] = ok ? make_key(make_float2(a.z, a.w), base + 2 * c + 1) : 0ull;
+            key[2 * j] = ok ? make_key(pr, z) : 0ull;
+            key[2 * j + 1] = ok ? make_key(pr, z ^ full) : 0ull;
         }
     }
-    const int cnt = (int)(CANON ? npair : span);
+    const int cnt = (int)(CANON ? span : 2 * span);
     const int q = k < cnt ? k : cnt;
     uint64_t prefix;
     int digits;

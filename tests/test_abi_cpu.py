@@ -33,8 +33,8 @@ def test_workspace_size_grows_with_state_and_gradient():
     a = _ws([14], [e])
     b = _ws([15], [e])
     c = _ws([15], [e], flags=_abi.QAOA_FLAG_GRADIENT)
-    assert 8 * (1 << 14) < a < b < c
-    assert c - b >= 8 * (1 << 15)  # the adjoint state
+    assert 8 * (1 << 13) < a < b < c  # the stored half-state of 14 qubits
+    assert c - b >= 8 * (1 << 14)  # the adjoint state
 
 
 @pytest.mark.parametrize("n,status", [(0, 2), (31, 2)])
@@ -154,7 +154,7 @@ def test_group_split_tuning_validation():
     _abi.qaoa_tune_group_split(26, [6, 8])
     _abi.qaoa_tune_group_split(26, [2, 4, 8])
     _abi.qaoa_tune_group_split(26, None)  # back to the default
-    for n, sizes, status in [(26, [7, 8], 1), (12, [1], 2), (31, [8, 8, 3], 2), (26, [9, 5], 2),
+    for n, sizes, status in [(26, [7, 8], 1), (13, [1], 2), (31, [8, 8, 3], 2), (26, [9, 5], 2),
                              (30, [6, 6, 6, 0], 2)]:
         with pytest.raises(_abi.QaoaError) as ei:
             _abi.qaoa_tune_group_split(n, sizes)

@@ -18,12 +18,12 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_autotune_candidates():
     from paper_2603_26232_amd.autotune import candidates, default_split
-    assert candidates(12) == [] and candidates(20) == [[8]]
+    assert candidates(12) == [] and candidates(13) == [] and candidates(20) == [[8]]
     assert candidates(21) == [[a, 9 - a] for a in range(1, 9)]
     assert [8, 8] in candidates(28) and len(candidates(28)) == 1
     c30 = candidates(30)
     assert all(len(x) == 3 and sum(x) == 18 and max(x) <= 8 for x in c30)
-    for n in range(13, 31):
+    for n in range(14, 31):
         d = default_split(n)
         assert sum(d) == n - 12 and max(d) - min(d) <= 1 and max(d) <= 8
         assert d in candidates(n) or len(candidates(n)) == 0
