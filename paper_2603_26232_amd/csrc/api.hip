@@ -776,14 +776,14 @@ MergePlan merge_plan(int32_t nV, int32_t M, int64_t nE, int32_t K, int32_t W)
         o += bytes;
         return r;
     };
-    const uint64_t nkeys = std::max<uint64_t>((uint64_t)W * K, 2ull * K);
+    const uint64_t nkeys = align_up(std::max<uint64_t>((uint64_t)W * K, 2ull * K), MERGE_KEY_PAD);
     P.o_lv = region(sizeof(MergeLevel) * M);
     P.o_intra = region(sizeof(int32_t) * 3 * (nE + 1));
     P.o_back = region(sizeof(int32_t) * 3 * (nE + 1));
     P.o_ccut = region(sizeof(int64_t) * M * K);
-    P.o_keys = region(sizeof(uint64_t) * nkeys);
+    P.o_keys = region(sizeof(uint32_t) * nkeys);
     P.o_surv = region(sizeof(Surv) * W);
-    P.o_counts = region(sizeof(int32_t) * 4);
+    P.o_counts = region(sizeof(int32_t) * (M + 1));
     P.o_rows0 = region(sizeof(uint32_t) * (uint64_t)W * P.nw);
     P.o_rows1 = region(sizeof(uint32_t) * (uint64_t)W * P.nw);
     P.o_scores = region(sizeof(int64_t) * W);
@@ -912,7 +912,7 @@ extern "C" qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const 
     m.intra = (const int32_t*)(ws + P.o_intra);
     m.back = (const int32_t*)(ws + P.o_back);
     m.ccut = (int64_t*)(ws + P.o_ccut);
-    m.keys = (uint64_t*)(ws + P.o_keys);
+    m.keys = (uint32_t*)(ws + P.o_keys);
     m.surv = (Surv*)(ws + P.o_surv);
     m.counts = (int32_t*)(ws + P.o_counts);
     m.rows[0] = (uint32_t*)(ws + P.o_rows0);

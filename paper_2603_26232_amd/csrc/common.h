@@ -100,9 +100,9 @@ struct MergeBufs {
     const int32_t* intra;
     const int32_t* back;
     int64_t* ccut;
-    uint64_t* keys;
+    uint32_t* keys;   // score + 1 per candidate (0 = none), index = path order
     Surv* surv;
-    int32_t* counts;  // [0] = current paths, [1] = survivors
+    int32_t* counts;  // [i] = paths at level i (M + 1 entries)
     uint32_t* rows[2];
     int64_t* scores;
 };
@@ -110,6 +110,7 @@ struct MergeBufs {
 hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV, const uint32_t* cand,
                         uint32_t* best, int64_t* best_cut, hipStream_t s);
 constexpr int MERGE_MAX_SIZE = 32;  // vertices per level (one uint32 bitstring)
+constexpr int MERGE_KEY_PAD = 65536;  // the key buffer holds a multiple of this many entries
 
 // ---- angle predictor (mlp.hip) ----
 constexpr int MLP_MAX_IN = 64, MLP_MAX_H = 256, MLP_MAX_OUT = 64;

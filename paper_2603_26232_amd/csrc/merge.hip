@@ -17,9 +17,10 @@
 // parent. After each level the W best paths by (score desc, path order asc)
 // survive; with W >= 2 K^(M-1) this is the exhaustive merge.
 //
-// Keys: (score + 1) << 32 | (0xFFFFFFFF - order), order = parent_rank * K + j
-// (level 1: 2j + o); zero marks an invalid candidate. Survivors are kept in
-// path order, so a survivor's rank is its position.
+// Keys: 32-bit, score + 1 (zero marks an invalid candidate); a key's index
+// in the level's key array is its path order, parent_rank * K + j (level 1:
+// 2j + o). Survivors are kept in path order, so a survivor's rank is its
+// position.
 #include "common.h"
 
 namespace pq {
@@ -51,15 +52,14 @@ __global__ void k_merge_intra(const MergeLevel* lv, const int32_t* intra, const 
 }
 
 // level 1: the 2 K_1 paths (j, o) in order b_1, ~b_1, b_2, ~b_2, ...
-__global__ void k_merge_first(const uint32_t* cand, int K, const int64_t* ccut, uint64_t* keys)
+__global__ void k_merge_first(const uint32_t* cand, int K, const int64_t* ccut, uint32_t* keys, int32_t* npaths)
 {
     const int Kv = level_k(cand, K, 0);
     for (int d = threadIdx.x; d < 2 * K; d += blockDim.x) {
         const int j = d >> 1;
-        uint64_t key = 0;
-        if (j < Kv) key = ((uint64_t)(ccut[j] + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)d);
-        keys[d] = key;
+        keys[d] = j < Kv ? (uint32_t)(ccut[j] + 1) : 0u;
     }
+    if (threadIdx.x == 0) npaths[0] = 1;
 }
 
 __device__ inline uint32_t row_bit(const uint32_t* row, int v) { return (row[v >> 5] >> (v & 31)) & 1u; }
@@ -67,12 +67,12 @@ __device__ inline uint32_t row_bit(const uint32_t* row, int v) { return (row[v >
 // level i >= 1: one block per parent path, one thread per candidate j
 __global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back, const uint32_t* cand, int K,
                                const int64_t* ccut, const uint32_t* rows, int nw, const int64_t* scores,
-                               const int32_t* npaths, uint64_t* keys)
+                               const int32_t* npaths, uint32_t* keys)
 {
     __shared__ int32_t A[32];
     const int p = blockIdx.x;
-    if (p >= *npaths) return;
-    const MergeLevel L = lv[i];
+    if (p >= npaths[i]) return;
+    const MergeLevel& L = lv[i];  // read in place (uniform loads), not copied
     const uint32_t* row = rows + (size_t)p * nw;
     if (threadIdx.x < 32) A[threadIdx.x] = 0;
     __syncthreads();
@@ -87,215 +87,248 @@ __global__ void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back,
     const int Kv = level_k(cand, K, i);
     const uint32_t xs = row_bit(row, L.start);
     const int64_t ps = scores[p];
+    const int size = L.size;
     for (int j = threadIdx.x; j < K; j += blockDim.x) {
-        uint64_t key = 0;
+        uint32_t key = 0;
         if (j < Kv) {
             const uint32_t b = cand[(size_t)i * K + j];
             const uint32_t o = (b & 1u) ^ xs;
             int64_t s = ps + ccut[(size_t)i * K + j];
-            for (int k = 1; k < L.size; ++k) {
+            for (int k = 1; k < size; ++k) {
                 const uint32_t y = ((b >> k) & 1u) ^ o;
                 s += y ? (L.wk[k] - (int64_t)A[k]) : (int64_t)A[k];
             }
-            const uint32_t order = (uint32_t)p * (uint32_t)K + (uint32_t)j;
-            key = ((uint64_t)(s + 1) << 32) | (uint64_t)(0xFFFFFFFFu - order);
+            key = (uint32_t)(s + 1);
         }
         keys[(size_t)p * K + j] = key;
     }
 }
 
 constexpr int SEL_THREADS = 1024;
-constexpr int SEL_BATCH = 8;
+constexpr int SEL_WAVES = SEL_THREADS / 64;
 constexpr int SEL_BINS = 4096;
+static_assert(SEL_THREADS * 64 == MERGE_KEY_PAD, "key buffer padding covers one resident round");
 
-__device__ inline int64_t key_score(uint64_t k) { return (int64_t)(k >> 32) - 1; }
-
-// block-wide exclusive scan of one int per thread (fixed order)
-__device__ inline int32_t block_exscan(int32_t x, int32_t* buf, int32_t* total)
+__device__ inline int32_t wave_sum(int32_t x)
 {
-    const int tid = threadIdx.x;
-    buf[tid] = x;
-    __syncthreads();
-    for (int off = 1; off < SEL_THREADS; off <<= 1) {
-        const int32_t y = tid >= off ? buf[tid - off] : 0;
-        __syncthreads();
-        buf[tid] += y;
-        __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline uint32_t wave_max(uint32_t x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(x, o, 64);
+        x = y > x ? y : x;
     }
-    const int32_t incl = buf[tid];
-    *total = buf[SEL_THREADS - 1];
-    __syncthreads();
-    return incl - x;
+    return x;
+}
+__device__ inline uint32_t wave_min(uint32_t x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+// exclusive prefix of the per-wave values slots[0..SEL_WAVES) at wave wv,
+// and their total (lanes 0..SEL_WAVES-1 read one slot each)
+__device__ inline void wave_slots_prefix(const int32_t* slots, int wv, int32_t& before, int32_t& total)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t v = lane < SEL_WAVES ? slots[lane] : 0;
+    int32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < SEL_WAVES; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    before = __shfl(incl - v, wv, 64);
+    total = __shfl(incl, SEL_WAVES - 1, 64);
+}
+// the value of x unknown to the optimiser (keeps it from holding values
+// derived from x live across the kernel instead of recomputing them)
+__device__ inline int32_t opaque(int32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
 }
 
 // Keep the Wsel best keys among keys[0..N) (N = paths * Kmul, key index =
-// path order) by (score desc, index asc) and write them as survivors in
-// index order. One workgroup: (1) best score and number of valid keys;
-// (2) histogram of (hi - score) over a window of 4096 scores to find the
-// threshold score s* at which the count reaches Wsel (the window slides down
-// if needed); (3) compaction in index order keeping every key above s* and
-// the first R keys equal to s*.
-__global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint64_t* keys, const int32_t* Nptr, int Kmul,
+// path order) by (key desc, index asc) and write them as survivors in index
+// order; the survivor count is the next level's path count. One workgroup;
+// the keys are visited in rounds of SEL_THREADS * PER, wave w of a round
+// holding keys [w * 64 PER, (w + 1) * 64 PER) of it in registers (64
+// consecutive keys per register). RESIDENT: N <= SEL_THREADS * PER (the
+// caller guarantees it), one round, the keys are read from memory once;
+// otherwise every step below re-reads them round by round. The key buffer
+// is padded to a multiple of MERGE_KEY_PAD entries, so every round reads in
+// bounds; entries at N and beyond are masked. (1) count, largest and
+// smallest valid key; (2) threshold key k* and the number R of keys equal to
+// k* that survive (every key above k* does), from histograms of
+// (hi - key) >> shift over [lo, hi] with 4096 bins, refined to the bin
+// holding the Wsel-th key until shift = 0 (at most three histograms for
+// 31-bit keys); (3) compaction in index order by wave ballots.
+template <int PER, bool RESIDENT>
+__global__ __launch_bounds__(SEL_THREADS) void k_merge_select(const uint32_t* keys, const int32_t* npaths, int Kmul,
                                                               int Wsel, int first, Surv* surv, int32_t* nsurv)
 {
     __shared__ int32_t hist[SEL_BINS];
-    __shared__ int32_t buf[SEL_THREADS];
-    __shared__ int64_t s_best;
-    __shared__ int32_t s_valid, s_found;
-    __shared__ int64_t s_star;
-    __shared__ int32_t s_R;
-    const int tid = threadIdx.x;
-    const int64_t N = (int64_t)(*Nptr) * Kmul;
-    if (tid == 0) {
-        s_best = 0;
-        s_valid = 0;
-    }
-    __syncthreads();
-    int64_t best = INT64_MIN;
+    __shared__ int32_t wa[SEL_WAVES], wb[SEL_WAVES];
+    __shared__ uint32_t s_hi, s_lo;
+    __shared__ int32_t s_above;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int32_t N = *npaths * Kmul;  // <= QAOA_MAX_BEAM * 2 QAOA_MAX_K
+    constexpr int32_t RW = SEL_THREADS * PER;
+    const int rounds = RESIDENT ? 1 : (N + RW - 1) / RW;
+    uint32_t sc[PER];
+    auto load = [&](int r) {
+        const int32_t b = opaque(r * RW + wv * 64 * PER + lane);
+        const uint32_t* kp = keys + b;
+        const int32_t lim = N - b;  // register j holds a key iff 64 j < lim
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t v = kp[64 * j];
+            sc[j] = 64 * j < lim ? v : 0u;
+        }
+    };
+    // (1)
     int32_t valid = 0;
-    // loads in batches of SEL_BATCH independent keys per thread (latency, not
-    // bandwidth, bounds a single workgroup)
-    for (int64_t q0 = tid; q0 < N; q0 += (int64_t)SEL_THREADS * SEL_BATCH) {
-        uint64_t kb[SEL_BATCH];
+    uint32_t mx = 0, mn = 0xFFFFFFFFu;  // mn: smallest valid key - 1
+    for (int r = 0; r < rounds; ++r) {
+        load(r);
 #pragma unroll
-        for (int j = 0; j < SEL_BATCH; ++j) {
-            const int64_t q = q0 + (int64_t)j * SEL_THREADS;
-            kb[j] = q < N ? keys[q] : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < SEL_BATCH; ++j) {
-            if (kb[j]) {
-                ++valid;
-                const int64_t sc = key_score(kb[j]);
-                best = sc > best ? sc : best;
-            }
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t k = sc[j];
+            valid += k != 0u;
+            mx = k > mx ? k : mx;
+            mn = k - 1u < mn ? k - 1u : mn;  // invalid (0) wraps to the maximum
         }
     }
-    atomicAdd(&s_valid, valid);
-    if (valid) atomicMax((unsigned long long*)&s_best, (unsigned long long)best);  // scores are >= 0
+    valid = wave_sum(valid);
+    mx = wave_max(mx);
+    mn = wave_min(mn);
+    if (lane == 0) {
+        wa[wv] = valid;
+        wb[wv] = (int32_t)mx;
+        hist[wv] = (int32_t)mn;
+    }
     __syncthreads();
-    const int32_t nvalid = s_valid;
-    const int64_t hi0 = s_best;
-    const int count = nvalid < Wsel ? nvalid : Wsel;
-    if (nvalid <= Wsel) {
-        if (tid == 0) {
-            s_star = INT64_MIN;  // every valid key is above the threshold
-            s_R = 0;
-        }
-    } else {
-        int64_t hi = hi0;
-        int32_t above = 0;  // keys with score > hi
+    int32_t nvalid, unused;
+    wave_slots_prefix(wa, 0, unused, nvalid);
+    uint32_t hi = wave_max(lane < SEL_WAVES ? (uint32_t)wb[lane] : 0u);
+    uint32_t lo = wave_min(lane < SEL_WAVES ? (uint32_t)hist[lane] : 0xFFFFFFFFu) + 1u;  // >= 1 if any valid
+    // (2)
+    uint32_t kstar = 0;  // nvalid <= Wsel: every valid key (> 0) survives
+    int32_t R = 0;
+    if (nvalid > Wsel) {
+        int32_t above = 0;  // keys above the current range [lo, hi]
         for (;;) {
-            for (int b = tid; b < SEL_BINS; b += SEL_THREADS) hist[b] = 0;
-            if (tid == 0) s_found = 0;
+            int shift = 0;
+            while (((hi - lo) >> shift) >= (uint32_t)SEL_BINS) ++shift;
+            __syncthreads();  // the previous reads of hist / wa are done
+            for (int c = tid; c < SEL_BINS; c += SEL_THREADS) hist[c] = 0;
             __syncthreads();
-            for (int64_t q0 = tid; q0 < N; q0 += (int64_t)SEL_THREADS * SEL_BATCH) {
-                uint64_t kb[SEL_BATCH];
+            for (int r = 0; r < rounds; ++r) {
+                if (!RESIDENT) load(r);
 #pragma unroll
-                for (int j = 0; j < SEL_BATCH; ++j) {
-                    const int64_t q = q0 + (int64_t)j * SEL_THREADS;
-                    kb[j] = q < N ? keys[q] : 0ull;
-                }
-#pragma unroll
-                for (int j = 0; j < SEL_BATCH; ++j) {
-                    if (!kb[j]) continue;
-                    const int64_t d = hi - key_score(kb[j]);
-                    if (d >= 0 && d < SEL_BINS) atomicAdd(&hist[d], 1);
+                for (int j = 0; j < PER; ++j) {
+                    const uint32_t k = sc[j];
+                    if (k >= lo && k <= hi) atomicAdd(&hist[(hi - k) >> shift], 1);  // lo >= 1: valid keys only
                 }
             }
             __syncthreads();
-            // each thread owns 4 consecutive bins
+            // thread t owns bins 4t .. 4t + 3; block exclusive scan of their sums
             int32_t h4[4], part = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                h4[i] = hist[4 * tid + i];
-                part += h4[i];
+            for (int c = 0; c < 4; ++c) {
+                h4[c] = hist[4 * tid + c];
+                part += h4[c];
             }
-            int32_t win_total;
-            const int32_t before = above + block_exscan(part, buf, &win_total);
-            int32_t run = before;
+            int32_t incl = part;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (run < Wsel && run + h4[i] >= Wsel) {
-                    s_star = hi - (4 * tid + i);
-                    s_R = Wsel - run;
-                    s_found = 1;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            if (lane == 63) wa[wv] = incl;
+            __syncthreads();
+            int32_t wbefore, wtotal;
+            wave_slots_prefix(wa, wv, wbefore, wtotal);
+            int32_t run = above + wbefore + incl - part;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (run < Wsel && run + h4[c] >= Wsel) {  // exactly one bin of one thread
+                    const uint32_t bin = (uint32_t)(4 * tid + c);
+                    s_above = run;
+                    s_hi = hi - (bin << shift);
+                    const uint32_t w = (bin << shift) + ((1u << shift) - 1u);  // hi - (the bin's lowest key)
+                    s_lo = (hi - lo > w) ? hi - w : lo;
                 }
-                run += h4[i];
+                run += h4[c];
             }
             __syncthreads();
-            if (s_found) break;
-            above += win_total;
-            hi -= SEL_BINS;
-            __syncthreads();
+            above = s_above;
+            hi = s_hi;
+            lo = s_lo;
+            if (shift == 0) {  // the bin is the single key value k*
+                kstar = hi;
+                R = Wsel - above;
+                break;
+            }
         }
     }
-    __syncthreads();
-    const int64_t star = s_star;
-    const int32_t R = s_R;
-    // compaction in index order: wave w owns keys [w*S, (w+1)*S), read 64
-    // consecutive keys at a time; ballots give each lane its rank among the
-    // wave's keys above / at the threshold, one barrier gives the wave bases
-    __shared__ int32_t wgt[SEL_THREADS / 64], weq[SEL_THREADS / 64];
-    const int lane = tid & 63, wv = tid >> 6;
-    constexpr int NWV = SEL_THREADS / 64;
-    const int64_t S = (N + NWV - 1) / NWV;
-    const int64_t lo = (int64_t)wv * S, up = lo + S < N ? lo + S : N;
+    // (3)
     const uint64_t below = (1ull << lane) - 1ull;
-    int32_t gt = 0, eq = 0;
-    for (int64_t b0 = lo; b0 < up; b0 += 64 * SEL_BATCH) {
-        uint64_t kb[SEL_BATCH];
+    int32_t carry_gt = 0, carry_eq = 0;
+    for (int r = 0; r < rounds; ++r) {
+        if (!RESIDENT) load(r);
+        int32_t gt = 0, eq = 0;
 #pragma unroll
-        for (int j = 0; j < SEL_BATCH; ++j) {
-            const int64_t q = b0 + 64 * j + lane;
-            kb[j] = q < up ? keys[q] : 0ull;
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t k = sc[j];
+            gt += k > kstar;
+            eq += k == kstar;  // kstar = 0 only if R = 0, where eq does not matter
         }
-#pragma unroll
-        for (int j = 0; j < SEL_BATCH; ++j) {
-            const uint64_t k = kb[j];
-            const int64_t sc = k ? key_score(k) : 0;
-            gt += __popcll(__ballot(k && sc > star));
-            eq += __popcll(__ballot(k && sc == star));
+        gt = wave_sum(gt);
+        eq = wave_sum(eq);
+        __syncthreads();  // wa / wb free
+        if (lane == 0) {
+            wa[wv] = gt;
+            wb[wv] = eq;
         }
-    }
-    if (lane == 0) {
-        wgt[wv] = gt;
-        weq[wv] = eq;
-    }
-    __syncthreads();
-    int32_t gt_before = 0, eq_before = 0;
-    for (int w = 0; w < wv; ++w) {
-        gt_before += wgt[w];
-        eq_before += weq[w];
-    }
-    for (int64_t b0 = lo; b0 < up; b0 += 64 * SEL_BATCH) {
-        uint64_t kb[SEL_BATCH];
+        __syncthreads();
+        int32_t gt_before, eq_before, gt_tot, eq_tot;
+        wave_slots_prefix(wa, wv, gt_before, gt_tot);
+        wave_slots_prefix(wb, wv, eq_before, eq_tot);
+        gt_before += carry_gt;
+        eq_before += carry_eq;
+        carry_gt += gt_tot;
+        carry_eq += eq_tot;
+        const int32_t b = opaque(r * RW + wv * 64 * PER + lane);
+        const uint32_t ks = (uint32_t)opaque((int32_t)kstar);  // recompute the ballots, do not keep them
 #pragma unroll
-        for (int j = 0; j < SEL_BATCH; ++j) {
-            const int64_t q = b0 + 64 * j + lane;
-            kb[j] = q < up ? keys[q] : 0ull;
-        }
-#pragma unroll
-        for (int j = 0; j < SEL_BATCH; ++j) {
-            const int64_t q = b0 + 64 * j + lane;
-            const uint64_t k = kb[j];
-            const int64_t sc = k ? key_score(k) : 0;
-            const bool g = k && sc > star, e = k && sc == star;
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t k = sc[j];
+            const bool g = k > ks, e = k == ks;
             const uint64_t bg = __ballot(g), be = __ballot(e);
             const int32_t my_gt = gt_before + __popcll(bg & below), my_eq = eq_before + __popcll(be & below);
             if (g || (e && my_eq < R)) {
+                const int32_t q = b + 64 * j;
                 const int pos = my_gt + (my_eq < R ? my_eq : R);
                 Surv sv;
-                sv.parent = first ? 0 : (int32_t)(q / Kmul);
-                sv.digit = first ? (int32_t)q : (int32_t)(q % Kmul);
-                sv.score = sc;
+                sv.parent = first ? 0 : q / Kmul;
+                sv.digit = first ? q : q % Kmul;
+                sv.score = opaque((int32_t)k) - 1;  // computed here, not hoisted for every register
                 surv[pos] = sv;
             }
             gt_before += __popcll(bg);
             eq_before += __popcll(be);
         }
     }
-    if (tid == 0) *nsurv = count;
+    if (tid == 0) *nsurv = nvalid < Wsel ? nvalid : Wsel;
 }
 
 // rows of the surviving paths: parent row prefix plus the bits of V_i
@@ -305,7 +338,7 @@ __global__ void k_merge_build(const MergeLevel* lv, int i, const uint32_t* cand,
 {
     const int r = blockIdx.x;
     if (r >= *nsurv) return;
-    const MergeLevel L = lv[i];
+    const MergeLevel& L = lv[i];
     const Surv s = surv[r];
     const int end = L.start + L.size;
     const int nwp = final_out ? nw : (end + 31) >> 5;
@@ -345,40 +378,35 @@ __global__ void k_merge_fail(uint32_t* out, int nw, int64_t* cut, const int32_t*
     if (threadIdx.x == 0) *cut = -1;
 }
 
-__global__ void k_set_count(int32_t* c, int v)
-{
-    if (threadIdx.x == 0) *c = v;
-}
-
-__global__ void k_copy_count(int32_t* c)
-{
-    if (threadIdx.x == 0) c[0] = c[1];
-}
-
 hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV, const uint32_t* cand,
                         uint32_t* best, int64_t* best_cut, hipStream_t s)
 {
     hipLaunchKernelGGL(k_merge_intra, dim3(M), dim3(64), 0, s, m.lv, m.intra, cand, K, m.ccut);
-    hipLaunchKernelGGL(k_merge_first, dim3(1), dim3(128), 0, s, cand, K, m.ccut, m.keys);
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, s, m.counts, 1);
+    hipLaunchKernelGGL(k_merge_first, dim3(1), dim3(128), 0, s, cand, K, m.ccut, m.keys, m.counts);
     int cur = 0;
     for (int i = 0; i < M; ++i) {
         const bool last = i == M - 1;
         const int wsel = last ? 1 : W;
+        const int kmul = i == 0 ? 2 * K : K;
+        const int64_t nmax = i == 0 ? 2 * K : (int64_t)W * K;  // keys at this level, at most
         if (i > 0)
             hipLaunchKernelGGL(k_merge_expand, dim3(W), dim3(64), 0, s, m.lv, i, m.back, cand, K, m.ccut,
                                m.rows[cur], nw, m.scores, m.counts, m.keys);
-        hipLaunchKernelGGL(k_merge_select, dim3(1), dim3(SEL_THREADS), 0, s, m.keys, m.counts,
-                           i == 0 ? 2 * K : K, wsel, i == 0 ? 1 : 0, m.surv, m.counts + 1);
+        // counts[i] = paths at level i, counts[i + 1] = its survivors
+        const int first = i == 0 ? 1 : 0;
+        if (nmax <= (int64_t)SEL_THREADS * 16)
+            hipLaunchKernelGGL((k_merge_select<16, true>), dim3(1), dim3(SEL_THREADS), 0, s, m.keys, m.counts + i,
+                               kmul, wsel, first, m.surv, m.counts + i + 1);
+        else if (nmax <= (int64_t)SEL_THREADS * 64)
+            hipLaunchKernelGGL((k_merge_select<64, true>), dim3(1), dim3(SEL_THREADS), 0, s, m.keys, m.counts + i,
+                               kmul, wsel, first, m.surv, m.counts + i + 1);
+        else
+            hipLaunchKernelGGL((k_merge_select<16, false>), dim3(1), dim3(SEL_THREADS), 0, s, m.keys, m.counts + i,
+                               kmul, wsel, first, m.surv, m.counts + i + 1);
         uint32_t* dst = last ? best : m.rows[cur ^ 1];
         hipLaunchKernelGGL(k_merge_build, dim3(last ? 1 : W), dim3(64), 0, s, m.lv, i, cand, K, m.surv,
-                           m.counts + 1, m.rows[cur], dst, nw, last ? best_cut : m.scores, last ? 1 : 0, nV);
-        if (last) {
-            hipLaunchKernelGGL(k_merge_fail, dim3(1), dim3(64), 0, s, best, nw, best_cut, m.counts + 1);
-        } else {
-            // survivors become the current paths
-            hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(64), 0, s, m.counts);
-        }
+                           m.counts + i + 1, m.rows[cur], dst, nw, last ? best_cut : m.scores, last ? 1 : 0, nV);
+        if (last) hipLaunchKernelGGL(k_merge_fail, dim3(1), dim3(64), 0, s, best, nw, best_cut, m.counts + M);
         cur ^= 1;
     }
     return hipGetLastError();

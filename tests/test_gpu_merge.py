@@ -50,7 +50,11 @@ def test_maxcut_eval_flags_bad_edge_ids():
 
 def _instance(seed, nV, N, K, raw=False, p_edge=0.1, weighted=False, ragged=False):
     g = synth.erdos_renyi(nV, p_edge, seed)
-    w = synth.random_weights(g.num_edges, seed + 1, 1, 4) if weighted else g.w
+    if weighted:
+        lo, hi = weighted if isinstance(weighted, tuple) else (1, 4)
+        w = synth.random_weights(g.num_edges, seed + 1, lo, hi)
+    else:
+        w = g.w
     g = synth.Graph(nV, g.u, g.v, w)
     if ragged:
         part = partition_chain(nV, synth.ragged_sizes(seed + 1, 3, N, 4 * nV))
@@ -73,6 +77,11 @@ def _instance(seed, nV, N, K, raw=False, p_edge=0.1, weighted=False, ragged=Fals
     (4, 400, 20, 16, 4096, False, False, False),  # the 400-vertex shape
     (5, 7, 7, 8, 3, False, False, False),       # a single subgraph
     (6, 300, 12, 5, 1, True, True, False),      # W = 1 (greedy)
+    # scores spread far beyond one 4096-bin histogram: the threshold is refined
+    (8, 120, 10, 16, 4096, False, (1, 100000), False),
+    # W K = 262144 keys: the selection re-reads them in rounds
+    (7, 160, 8, 32, 8192, False, (1, 200000), False),
+    (9, 160, 8, 32, 8192, True, False, True),
 ])
 def test_merge_matches_oracle(seed, nV, N, K, W, raw, weighted, ragged):
     g, part, cand = _instance(seed, nV, N, K, raw=raw, weighted=weighted, ragged=ragged)
