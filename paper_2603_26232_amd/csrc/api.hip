@@ -761,7 +761,8 @@ extern "C" qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* ou
 // ---------------------------------------------------------------------------
 namespace {
 struct MergePlan {
-    uint64_t o_lv, o_intra, o_back, o_ccut, o_keys, o_surv, o_counts, o_rows0, o_rows1, o_scores, total;
+    uint64_t o_lv, o_intra, o_back, o_ccut, o_keys, o_surv, o_counts, o_rows0, o_rows1, o_scores, o_lvs, o_maxinc,
+        o_hist, o_below, o_pcnt, total;
     int nw;
 };
 
@@ -787,6 +788,11 @@ MergePlan merge_plan(int32_t nV, int32_t M, int64_t nE, int32_t K, int32_t W)
     P.o_rows0 = region(sizeof(uint32_t) * (uint64_t)W * P.nw);
     P.o_rows1 = region(sizeof(uint32_t) * (uint64_t)W * P.nw);
     P.o_scores = region(sizeof(int64_t) * W);
+    P.o_lvs = region(sizeof(MergeLvState) * (M + 1));
+    P.o_maxinc = region(sizeof(uint32_t) * M);
+    P.o_hist = region(sizeof(int32_t) * MERGE_HIST_INTS);
+    P.o_below = region(sizeof(int32_t));
+    P.o_pcnt = region(sizeof(int64_t) * W);
     P.total = align_up(o, 4096);
     return P;
 }
@@ -918,6 +924,11 @@ extern "C" qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const 
     m.rows[0] = (uint32_t*)(ws + P.o_rows0);
     m.rows[1] = (uint32_t*)(ws + P.o_rows1);
     m.scores = (int64_t*)(ws + P.o_scores);
+    m.lvs = (MergeLvState*)(ws + P.o_lvs);
+    m.maxinc = (uint32_t*)(ws + P.o_maxinc);
+    m.hist = (int32_t*)(ws + P.o_hist);
+    m.below = (int32_t*)(ws + P.o_below);
+    m.pcnt = (int64_t*)(ws + P.o_pcnt);
     ProfScope ps("merge", st, 0.0);
     HIP_TRY(launch_merge(m, M, K, W, P.nw, num_vertices, d_cand, d_best_assign, d_best_cut, st));
     return ok();

@@ -95,16 +95,31 @@ struct Surv {
     int64_t score;
 };
 
+// per level: the selection's outcome
+struct MergeLvState {
+    uint32_t best;   // largest key (score + 1) of the level
+    uint32_t kstar;  // keys above kstar survive ...
+    int32_t R;       // ... and the first R keys equal to it
+    int32_t count;   // survivors
+};
+
+constexpr int MERGE_HIST_INTS = 65536 + 4096;  // fine + coarse bins
+
 struct MergeBufs {
     const MergeLevel* lv;
     const int32_t* intra;
     const int32_t* back;
     int64_t* ccut;
     uint32_t* keys;   // score + 1 per candidate (0 = none), index = path order
-    Surv* surv;
+    Surv* surv;       // level 1's survivors
     int32_t* counts;  // [i] = paths at level i (M + 1 entries)
     uint32_t* rows[2];
     int64_t* scores;
+    MergeLvState* lvs;  // [M]
+    uint32_t* maxinc;   // [M] largest possible score increment of level i
+    int32_t* hist;      // [MERGE_HIST_INTS]
+    int32_t* below;     // keys below the histogram's window
+    int64_t* pcnt;      // [W] per parent: survivors above (low) / at (high) the threshold
 };
 
 hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV, const uint32_t* cand,

@@ -82,6 +82,7 @@ def _instance(seed, nV, N, K, raw=False, p_edge=0.1, weighted=False, ragged=Fals
     # W K = 262144 keys: the selection re-reads them in rounds
     (7, 160, 8, 32, 8192, False, (1, 200000), False),
     (9, 160, 8, 32, 8192, True, False, True),
+    (10, 200, 12, 64, 512, False, False, False),  # K = 64: a parent's children fill a wave
 ])
 def test_merge_matches_oracle(seed, nV, N, K, W, raw, weighted, ragged):
     g, part, cand = _instance(seed, nV, N, K, raw=raw, weighted=weighted, ragged=ragged)
