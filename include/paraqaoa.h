@@ -19,10 +19,13 @@
  *     named in "host" comments are host pointers. The caller owns every
  *     buffer, device and host; the library never frees caller memory.
  *   - Every call that takes a stream only enqueues work on it and never
- *     synchronises the device, except qaoa_batch_create and
- *     qaoa_merge_beam, which copy host arrays to the device and wait for
- *     that copy. Outputs are valid once the caller synchronises the stream.
- *     A handle must not be used by two host threads at once.
+ *     synchronises the device. qaoa_batch_create and qaoa_merge_beam copy
+ *     the host arrays they need into one of four pinned staging buffers
+ *     owned by the library (used in turn, kept until the process ends,
+ *     grown as needed) and enqueue the upload on `stream`; the host arrays
+ *     may be reused on return. A call waits only if the upload made four
+ *     calls earlier has not yet left its staging buffer. Outputs are valid once the caller synchronises the
+ *     stream. A handle must not be used by two host threads at once.
  *   - Errors are reported as status codes only; nothing aborts or throws.
  *     All arguments are checked before any work is enqueued; on an error
  *     no work is enqueued and qaoa_last_error() holds a message

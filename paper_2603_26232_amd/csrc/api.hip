@@ -43,6 +43,63 @@ static qaoa_status_t ok()
     } while (0)
 
 // ---------------------------------------------------------------------------
+// host-to-device uploads of metadata images: a ring of pinned staging
+// buffers, each grown as needed and reused once the copy from it has
+// completed (an event recorded after the copy). An upload enqueues without
+// waiting for the stream's earlier work; it waits only if the slot's
+// previous upload (STAGE_SLOTS uploads ago) has not left it yet.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int STAGE_SLOTS = 4;
+struct StageSlot {
+    void* buf = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    int dev = -1;
+    bool pending = false;
+};
+struct Staging {
+    std::mutex mu;
+    StageSlot slot[STAGE_SLOTS];
+    int next = 0;
+};
+Staging g_stage;
+}  // namespace
+
+static qaoa_status_t upload_async(void* d_dst, const void* src, size_t bytes, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    StageSlot& S = g_stage.slot[g_stage.next];
+    g_stage.next = (g_stage.next + 1) % STAGE_SLOTS;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (S.pending) {
+        HIP_TRY(hipEventSynchronize(S.ev));  // the slot's buffer is free again
+        S.pending = false;
+    }
+    if (S.ev && S.dev != dev) {
+        HIP_TRY(hipEventDestroy(S.ev));
+        S.ev = nullptr;
+    }
+    if (!S.ev) {
+        HIP_TRY(hipEventCreateWithFlags(&S.ev, hipEventDisableTiming));
+        S.dev = dev;
+    }
+    if (bytes > S.cap) {
+        if (S.buf) HIP_TRY(hipHostFree(S.buf));
+        S.buf = nullptr;
+        S.cap = 0;
+        HIP_TRY(hipHostMalloc(&S.buf, bytes, hipHostMallocPortable));
+        S.cap = bytes;
+    }
+    memcpy(S.buf, src, bytes);
+    HIP_TRY(hipMemcpyAsync(d_dst, S.buf, bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(S.ev, st));
+    S.pending = true;
+    return QAOA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // kernel timing (measurement hook)
 // ---------------------------------------------------------------------------
 namespace {
@@ -552,13 +609,8 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
     }
     hipStream_t st = (hipStream_t)stream;
     uint8_t* ws = (uint8_t*)d_workspace;
-    void* pinned = nullptr;
-    HIP_TRY(hipHostMalloc(&pinned, meta_end, hipHostMallocDefault));
-    memcpy(pinned, img.data(), meta_end);
-    hipError_t e1 = hipMemcpyAsync(ws, pinned, meta_end, hipMemcpyHostToDevice, st);
-    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(st) : e1;
-    (void)hipHostFree(pinned);
-    if (e2 != hipSuccess) return fail(QAOA_ERR_HIP, "metadata upload: %s", hipGetErrorString(e2));
+    s = upload_async(ws, img.data(), meta_end, st);
+    if (s != QAOA_OK) return s;
 
     qaoa_batch_s* h = new qaoa_batch_s();
     h->P = std::move(P);
@@ -906,13 +958,8 @@ extern "C" qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const 
     memcpy(img.data() + P.o_lv, lv.data(), sizeof(MergeLevel) * M);
     hipStream_t st = (hipStream_t)stream;
     uint8_t* ws = (uint8_t*)d_workspace;
-    void* pinned = nullptr;
-    HIP_TRY(hipHostMalloc(&pinned, meta_end, hipHostMallocDefault));
-    memcpy(pinned, img.data(), meta_end);
-    hipError_t e1 = hipMemcpyAsync(ws, pinned, meta_end, hipMemcpyHostToDevice, st);
-    hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(st) : e1;
-    (void)hipHostFree(pinned);
-    if (e2 != hipSuccess) return fail(QAOA_ERR_HIP, "merge metadata upload: %s", hipGetErrorString(e2));
+    s = upload_async(ws, img.data(), meta_end, st);
+    if (s != QAOA_OK) return s;
     MergeBufs m;
     m.lv = (const MergeLevel*)(ws + P.o_lv);
     m.intra = (const int32_t*)(ws + P.o_intra);

@@ -64,6 +64,8 @@ class Solver:
                                skip_edgeless=skip_edgeless, device=dev)
         P = self.B * cfg.p
         self.theta = torch.zeros(2 * P, dtype=torch.float64, device=dev)   # [gamma | beta]
+        self._theta_host = torch.zeros(2 * P, dtype=torch.float64, pin_memory=dev.type == "cuda")
+        self._theta_copied = None  # event after the last copy out of _theta_host
         self.grad = torch.zeros(2 * P, dtype=torch.float64, device=dev)    # [dgamma | dbeta]
         self.m = torch.zeros(2 * P, dtype=torch.float64, device=dev)
         self.v = torch.zeros(2 * P, dtype=torch.float64, device=dev)
@@ -96,8 +98,19 @@ class Solver:
 
     def set_angles(self, gamma, beta):
         P = self.B * self.cfg.p
-        self.theta[:P] = torch.as_tensor(np.asarray(gamma).reshape(-1), dtype=torch.float64)
-        self.theta[P:] = torch.as_tensor(np.asarray(beta).reshape(-1), dtype=torch.float64)
+        host = np.concatenate([np.asarray(gamma, dtype=np.float64).reshape(-1),
+                               np.asarray(beta, dtype=np.float64).reshape(-1)])
+        assert host.size == 2 * P
+        # persistent pinned staging + asynchronous copy: the host waits only
+        # for the previous copy out of the staging buffer (allocating or
+        # freeing pinned memory here would wait for the whole device)
+        if self._theta_copied is not None:
+            self._theta_copied.synchronize()
+        self._theta_host.numpy()[:] = host
+        self.theta.copy_(self._theta_host, non_blocking=True)
+        if self._theta_copied is None:
+            self._theta_copied = torch.cuda.Event()
+        self._theta_copied.record()
         self.m.zero_()
         self.v.zero_()
         self.step.zero_()

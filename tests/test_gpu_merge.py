@@ -97,6 +97,32 @@ def test_merge_matches_oracle(seed, nV, N, K, W, raw, weighted, ragged):
         assert ex[0] == ref_cut and np.array_equal(ex[1], got_x)
 
 
+def test_merge_host_arrays_reusable_after_call():
+    """qaoa_merge_beam stages its host arrays before returning: overwriting
+    them right after the call changes nothing."""
+    from paper_2603_26232_amd import _abi
+    g, part, cand = _instance(11, 200, 12, 16, 4096)
+    dcand = torch.as_tensor(cand.view(np.int32), device="cuda")
+    busy = torch.randn(4096, 4096, device="cuda")
+    for _ in range(4):
+        busy = busy @ busy  # queued work ahead of the upload
+        busy /= busy.abs().max()
+    start, size = part.start.astype(np.int32).copy(), part.size.astype(np.int32).copy()
+    u, v, w = g.u.astype(np.int32).copy(), g.v.astype(np.int32).copy(), g.w.astype(np.int32).copy()
+    nw = (g.num_vertices + 31) // 32
+    mb = _abi.qaoa_merge_workspace_bytes(g.num_vertices, part.M, g.num_edges, 16, 4096)
+    ws = torch.empty(mb, dtype=torch.uint8, device="cuda")
+    best = torch.zeros(nw, dtype=torch.int32, device="cuda")
+    cut = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _abi.qaoa_merge_beam(g.num_vertices, part.M, start, size, g.num_edges, u, v, w, 16, dcand.data_ptr(), 4096,
+                         ws.data_ptr(), mb, best.data_ptr(), cut.data_ptr(), 0)
+    for a in (start, size, u, v, w):
+        a[...] = -1
+    ref_cut, ref_x, _, _ = oracle.merge(g.num_vertices, part.start, part.size, g.u, g.v, g.w, cand, W=4096)
+    assert int(cut.cpu()[0]) == ref_cut
+    assert np.array_equal(_unpack(best.cpu().numpy(), g.num_vertices), ref_x)
+
+
 def test_merge_rejects_bad_chains():
     g = synth.erdos_renyi(10, 0.3, 0)
     cand = torch.zeros((2, 2), dtype=torch.int32, device="cuda")

@@ -313,3 +313,32 @@ def test_wide_cut_tables():
         assert np.max(np.abs(dg.cpu().numpy()[b] - g_ref)) <= G_TOL * scale
         assert np.max(np.abs(db.cpu().numpy()[b] - b_ref)) <= G_TOL * scale
     bt.close()
+
+
+def test_host_arrays_reusable_after_create(monkeypatch):
+    """qaoa_batch_create stages its host arrays before returning: overwriting
+    them right after the call, while the upload still waits behind earlier
+    work on the stream, changes nothing."""
+    from paper_2603_26232_amd import _abi
+    busy_sizes = [24] * 4
+    busy = QaoaBatch(busy_sizes, _subgraphs(busy_sizes, 7, p_edge=0.2), max_p=4, max_k=8)
+    g4, b4 = synth.uniform_angles(99, 4, batch=4)
+    busy.apply_layers(g4, b4)  # queued work ahead of the upload
+    sizes = [14, 18]
+    edges = _subgraphs(sizes, 321)
+    gamma, beta = synth.uniform_angles(4321, 2, batch=len(sizes))
+    orig = _abi.qaoa_batch_create
+
+    def create_then_overwrite(B, nq, off, u, v, w, *rest):
+        h = orig(B, nq, off, u, v, w, *rest)
+        for a in (off, u, v, w):  # (the batch object keeps nq as its sizes)
+            a[...] = -1
+        return h
+
+    monkeypatch.setattr(_abi, "qaoa_batch_create", create_then_overwrite)
+    bt = QaoaBatch(sizes, edges, max_p=2, max_k=8)
+    monkeypatch.undo()
+    bt.apply_layers(gamma, beta)
+    _check_states(bt, sizes, edges, gamma, beta)
+    bt.close()
+    busy.close()
