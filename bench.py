@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "QAOA amp-updates/s + HBM GB/s; 2k-vertex solve time, learned vs plain angles"
 PASSES = [f"fwd_{k}_g{g}" for k in ("first", "single", "mid", "last") for g in range(4)] + \
     [f"bwd_{k}_g{g}" for k in ("fused", "single", "mid", "last", "single_nopsi", "mid_nopsi") for g in range(4)]
-KERNELS = PASSES + ["small", "cut_tables", "angle_prep", "reduce", "topk", "maxcut", "adam", "merge"]
+KERNELS = PASSES + ["small", "cut_tables", "angle_prep", "reduce", "reduce_adam", "topk", "maxcut", "adam", "merge"]
 HBM_PEAK_GBS = 8000.0
 
 

@@ -177,6 +177,28 @@ qaoa_status_t qaoa_adam_step(int32_t count, double* d_theta, const double* d_gra
                              int32_t* d_step, double lr, double beta1, double beta2, double eps,
                              int32_t maximise, qaoa_stream_t stream);
 
+/* `iters` steps of the angle optimisation of Sec. 2.2, all on the device:
+ * each step evaluates every subgraph's <C> and its exact gradient at theta
+ * (as qaoa_expectation_grad) and takes one FP64 Adam ascent step on the
+ * angles (as qaoa_adam_step with count = 2*B*p, maximise = 1). Per step, the
+ * gradient's reduction, the Adam update and the preparation of the next
+ * step's rotation and phase tables run as one kernel; the results are
+ * bit-identical to the two separate calls per step. Needs QAOA_FLAG_GRADIENT.
+ *   p          1..max_p
+ *   iters      >= 0 (0: nothing is enqueued)
+ *   d_theta    device double [2*B*p], [gamma (row b = subgraph b, B*p) |
+ *              beta (B*p)], updated in place
+ *   d_m, d_v   device double [2*B*p], Adam moments (start at zero)
+ *   d_step     device int32 [1], Adam steps taken so far; +iters on completion
+ *   lr, beta1, beta2, eps  the Adam constants (as qaoa_adam_step)
+ *   d_E        device double [B] receiving <C> at the angles each step
+ *              starts from (the last step's remains), or NULL
+ * The state is consumed (call qaoa_apply_layers before qaoa_topk). Calls on
+ * one batch must not overlap (they share a counter in the workspace). */
+qaoa_status_t qaoa_optimize(qaoa_batch_t h, int32_t p, int32_t iters, double* d_theta, double* d_m, double* d_v,
+                            int32_t* d_step, double lr, double beta1, double beta2, double eps, double* d_E,
+                            qaoa_stream_t stream);
+
 /* CutVal (Sec. 2.1) of num_assign full-graph assignments, as the merge of
  * Alg. 2 evaluates each concatenated bitstring over all edges of G.
  *   d_u, d_v   device int32 [num_edges] vertex ids

@@ -67,6 +67,7 @@ def lib() -> ct.CDLL:
             "qaoa_topk": [_vp, _i32, _vp, _vp, _vp],
             "qaoa_expectation_grad": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
             "qaoa_adam_step": [_i32, _vp, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _i32, _vp],
+            "qaoa_optimize": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _f64, _f64, _f64, _f64, _vp, _vp],
             "maxcut_eval": [_i32, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp],
             "qaoa_merge_workspace_bytes": [_i32, _i32, _i64, _i32, _i32, _vp],
             "qaoa_merge_beam": [_i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _i32, _vp,
@@ -174,6 +175,12 @@ def qaoa_adam_step(count: int, d_theta: int, d_grad: int, d_m: int, d_v: int, d_
                    beta1: float, beta2: float, eps: float, maximise: int, stream: int) -> None:
     _call("qaoa_adam_step", count, _vp(d_theta), _vp(d_grad), _vp(d_m), _vp(d_v), _vp(d_step), lr,
           beta1, beta2, eps, maximise, _vp(stream))
+
+
+def qaoa_optimize(h: int, p: int, iters: int, d_theta: int, d_m: int, d_v: int, d_step: int, lr: float,
+                  beta1: float, beta2: float, eps: float, d_E: int, stream: int) -> None:
+    _call("qaoa_optimize", _vp(h), p, iters, _vp(d_theta), _vp(d_m), _vp(d_v), _vp(d_step), lr, beta1, beta2, eps,
+          _vp(d_E), _vp(stream))
 
 
 def maxcut_eval(num_vertices: int, num_edges: int, d_u: int, d_v: int, d_w, num_assign: int,

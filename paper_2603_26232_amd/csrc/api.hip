@@ -196,7 +196,8 @@ struct Plan {
     int64_t total_edges = 0;
     int lut_max = 1;
     // region offsets
-    uint64_t o_subs = 0, o_work_all = 0, o_small = 0, o_edges = 0, o_coef = 0, o_lut = 0, o_pe = 0, o_pgb = 0,
+    uint64_t o_subs = 0, o_work_all = 0, o_small = 0, o_edges = 0, o_sync = 0, o_coef = 0, o_lut = 0, o_pe = 0,
+             o_pgb = 0,
              o_pgg = 0, o_keys = 0, total = 0;
     int nsmall = 0;
     // host images of the metadata regions
@@ -364,6 +365,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     for (auto& c : P.classes) c.o_work = region(sizeof(int2) * c.work.size(), 256);
     P.o_small = region(sizeof(int32_t) * (P.nsmall + 1), 256);
     P.o_edges = region(sizeof(int32_t) * 3 * (P.total_edges + 1), 256);
+    P.o_sync = region(256, 256);  // block-arrival counter of the fused optimiser kernel (uploaded as zero)
     P.o_coef = region(sizeof(RxCoef) * B * max_p, 256);
     uint64_t lut_total = 0;
     for (int b = 0; b < B; ++b) lut_total += (uint64_t)max_p * P.subs[b].lut_len;
@@ -712,21 +714,11 @@ extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, f
     return ok();
 }
 
-extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const double* d_gamma,
-                                               const double* d_beta, double* d_E, double* d_dgamma,
-                                               double* d_dbeta, qaoa_stream_t stream)
+// the small-subgraph kernel and every tile pass of one gradient evaluation
+// (forward sweep, fused turn, adjoint sweep), after the angle tables are set
+static qaoa_status_t enqueue_grad_passes(qaoa_batch_t h, int32_t p, hipStream_t st)
 {
-    qaoa_status_t s = check_angles(h, p, d_gamma, d_beta);
-    if (s != QAOA_OK) return s;
-    if (!(h->P.flags & QAOA_FLAG_GRADIENT))
-        return fail(QAOA_ERR_STATE, "batch was created without QAOA_FLAG_GRADIENT");
-    if (!d_E || !d_dgamma || !d_dbeta) return fail(QAOA_ERR_INVALID_ARG, "output pointers are NULL");
-    hipStream_t st = (hipStream_t)stream;
     Plan& P = h->P;
-    {
-        ProfScope ps("angle_prep", st, angle_bytes(P, p));
-        HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
-    }
     if (P.nsmall) {
         ProfScope ps("small", st, small_bytes(P, p, true));
         HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 1, h->part,
@@ -761,9 +753,67 @@ extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const 
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }
     }
+    return QAOA_OK;
+}
+
+extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const double* d_gamma,
+                                               const double* d_beta, double* d_E, double* d_dgamma,
+                                               double* d_dbeta, qaoa_stream_t stream)
+{
+    qaoa_status_t s = check_angles(h, p, d_gamma, d_beta);
+    if (s != QAOA_OK) return s;
+    if (!(h->P.flags & QAOA_FLAG_GRADIENT))
+        return fail(QAOA_ERR_STATE, "batch was created without QAOA_FLAG_GRADIENT");
+    if (!d_E || !d_dgamma || !d_dbeta) return fail(QAOA_ERR_INVALID_ARG, "output pointers are NULL");
+    hipStream_t st = (hipStream_t)stream;
+    Plan& P = h->P;
+    {
+        ProfScope ps("angle_prep", st, angle_bytes(P, p));
+        HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
+    }
+    s = enqueue_grad_passes(h, p, st);
+    if (s != QAOA_OK) return s;
     {
         ProfScope ps("reduce", st, 8.0 * P.total_tiles * (1.0 + p * (MAX_GROUPS + 1.0)));
         HIP_TRY(launch_reduce(h->d_subs, P.B, p, 1, h->part, d_E, d_dgamma, d_dbeta, st));
+    }
+    h->state_valid = false;
+    h->e_valid = true;
+    return ok();
+}
+
+static bool adam_constants_ok(double lr, double beta1, double beta2, double eps)
+{
+    return beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && lr >= 0.0;
+}
+
+extern "C" qaoa_status_t qaoa_optimize(qaoa_batch_t h, int32_t p, int32_t iters, double* d_theta, double* d_m,
+                                       double* d_v, int32_t* d_step, double lr, double beta1, double beta2,
+                                       double eps, double* d_E, qaoa_stream_t stream)
+{
+    if (!d_theta) return fail(QAOA_ERR_INVALID_ARG, "d_theta is NULL");
+    qaoa_status_t s = check_angles(h, p, d_theta, d_theta + (size_t)(h ? h->P.B : 0) * p);
+    if (s != QAOA_OK) return s;
+    if (!(h->P.flags & QAOA_FLAG_GRADIENT))
+        return fail(QAOA_ERR_STATE, "batch was created without QAOA_FLAG_GRADIENT");
+    if (iters < 0) return fail(QAOA_ERR_INVALID_ARG, "iters = %d must be >= 0", iters);
+    if (!d_m || !d_v || !d_step) return fail(QAOA_ERR_INVALID_ARG, "d_m/d_v/d_step are NULL");
+    if (!adam_constants_ok(lr, beta1, beta2, eps)) return fail(QAOA_ERR_OUT_OF_RANGE, "Adam constants out of range");
+    if (iters == 0) return ok();
+    hipStream_t st = (hipStream_t)stream;
+    Plan& P = h->P;
+    const size_t BP = (size_t)P.B * p;
+    {
+        ProfScope ps("angle_prep", st, angle_bytes(P, p));
+        HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_theta, d_theta + BP, st));
+    }
+    for (int it = 0; it < iters; ++it) {
+        s = enqueue_grad_passes(h, p, st);
+        if (s != QAOA_OK) return s;
+        ProfScope ps("reduce_adam", st,
+                     8.0 * P.total_tiles * (1.0 + p * (MAX_GROUPS + 1.0)) + 7.0 * 8.0 * 2.0 * BP + angle_bytes(P, p));
+        HIP_TRY(launch_reduce_adam(h->ws, h->d_subs, P.B, p, h->part, d_theta, d_m, d_v, d_step,
+                                   (int32_t*)(h->ws + P.o_sync), lr, beta1, beta2, eps, d_E, st));
     }
     h->state_valid = false;
     h->e_valid = true;
@@ -776,8 +826,7 @@ extern "C" qaoa_status_t qaoa_adam_step(int32_t count, double* d_theta, const do
 {
     if (count < 1) return fail(QAOA_ERR_INVALID_ARG, "count = %d must be >= 1", count);
     if (!d_theta || !d_grad || !d_m || !d_v || !d_step) return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
-    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && lr >= 0.0))
-        return fail(QAOA_ERR_OUT_OF_RANGE, "Adam constants out of range");
+    if (!adam_constants_ok(lr, beta1, beta2, eps)) return fail(QAOA_ERR_OUT_OF_RANGE, "Adam constants out of range");
     hipStream_t st = (hipStream_t)stream;
     ProfScope ps("adam", st, 7.0 * 8.0 * count);
     HIP_TRY(launch_adam(count, d_theta, d_grad, d_m, d_v, d_step, lr, beta1, beta2, eps, maximise ? 1.0 : -1.0, st));
@@ -814,7 +863,7 @@ extern "C" qaoa_status_t qaoa_state_offset(qaoa_batch_t h, int32_t b, size_t* ou
 namespace {
 struct MergePlan {
     uint64_t o_lv, o_intra, o_back, o_ccut, o_keys, o_surv, o_counts, o_rows0, o_rows1, o_scores, o_lvs, o_maxinc,
-        o_hist, o_below, o_pcnt, total;
+        o_hist, o_below, o_pcnt, o_lvk, total;
     int nw;
 };
 
@@ -845,6 +894,7 @@ MergePlan merge_plan(int32_t nV, int32_t M, int64_t nE, int32_t K, int32_t W)
     P.o_hist = region(sizeof(int32_t) * MERGE_HIST_INTS);
     P.o_below = region(sizeof(int32_t));
     P.o_pcnt = region(sizeof(int64_t) * W);
+    P.o_lvk = region(sizeof(int32_t) * M);
     P.total = align_up(o, 4096);
     return P;
 }
@@ -976,6 +1026,7 @@ extern "C" qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const 
     m.hist = (int32_t*)(ws + P.o_hist);
     m.below = (int32_t*)(ws + P.o_below);
     m.pcnt = (int64_t*)(ws + P.o_pcnt);
+    m.lvk = (int32_t*)(ws + P.o_lvk);
     ProfScope ps("merge", st, 0.0);
     HIP_TRY(launch_merge(m, M, K, W, P.nw, num_vertices, d_cand, d_best_assign, d_best_cut, st));
     return ok();

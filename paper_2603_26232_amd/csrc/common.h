@@ -117,6 +117,7 @@ struct MergeBufs {
     int64_t* scores;
     MergeLvState* lvs;  // [M]
     uint32_t* maxinc;   // [M] largest possible score increment of level i
+    int32_t* lvk;       // [M] valid candidates of level i
     int32_t* hist;      // [MERGE_HIST_INTS]
     int32_t* below;     // keys below the histogram's window
     int64_t* pcnt;      // [W] per parent: survivors above (low) / at (high) the threshold
@@ -164,6 +165,27 @@ hipError_t launch_topk(uint8_t* ws, const SubDesc* subs, const int2* work, int n
 hipError_t launch_maxcut_eval(int32_t nV, int64_t nE, const int32_t* u, const int32_t* v,
                               const int32_t* w, int64_t A, const uint32_t* assign, int64_t* cut,
                               hipStream_t s);
+// Adam (Kingma and Ba 2015) update of one parameter in FP64 with the bias
+// corrections c1 = 1 - b1^t, c2 = 1 - b2^t; sign +1 ascends. The standalone
+// step and the fused optimiser kernel share it; every operation is an
+// explicitly rounded one (no contraction into FMAs, which the compiler could
+// choose differently in the two kernels), so both give the same bits.
+__device__ __noinline__ inline void adam_update(double& th, double& m, double& v, double g, double c1, double c2, double lr,
+                                   double b1, double b2, double eps, double sign)
+{
+    const double mi = __dadd_rn(__dmul_rn(b1, m), __dmul_rn(__dsub_rn(1.0, b1), g));
+    const double vi = __dadd_rn(__dmul_rn(b2, v), __dmul_rn(__dmul_rn(__dsub_rn(1.0, b2), g), g));
+    m = mi;
+    v = vi;
+    const double step = __ddiv_rn(__dmul_rn(__dmul_rn(sign, lr), __ddiv_rn(mi, c1)),
+                                  __dadd_rn(__dsqrt_rn(__ddiv_rn(vi, c2)), eps));
+    th = __dadd_rn(th, step);
+}
+// reduction of the gradient, Adam ascent step and the next step's tables,
+// one block per (subgraph, layer) (sim.hip)
+hipError_t launch_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p, Partials part, double* theta,
+                              double* m, double* v, int32_t* step, int32_t* arrive, double lr, double b1, double b2,
+                              double eps, double* E, hipStream_t s);
 hipError_t launch_adam(int32_t count, double* theta, const double* grad, double* m, double* v,
                        int32_t* step, double lr, double b1, double b2, double eps, double sign,
                        hipStream_t s);

@@ -63,12 +63,11 @@ __global__ __launch_bounds__(1024) void k_adam(int32_t count, double* theta, con
     const int32_t t = *step + 1;
     const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
     for (int32_t i = threadIdx.x; i < count; i += blockDim.x) {
-        const double g = grad[i];
-        const double mi = b1 * m[i] + (1.0 - b1) * g;
-        const double vi = b2 * v[i] + (1.0 - b2) * g * g;
+        double th = theta[i], mi = m[i], vi = v[i];
+        adam_update(th, mi, vi, grad[i], c1, c2, lr, b1, b2, eps, sign);
         m[i] = mi;
         v[i] = vi;
-        theta[i] += sign * lr * (mi / c1) / (sqrt(vi / c2) + eps);
+        theta[i] = th;
     }
     __syncthreads();
     if (threadIdx.x == 0) *step = t;

@@ -42,13 +42,6 @@
 
 namespace pq {
 
-__device__ inline int level_k(const uint32_t* cand, int K, int i)
-{
-    int k = 0;
-    while (k < K && cand[(size_t)i * K + k] != 0xFFFFFFFFu) ++k;
-    return k;
-}
-
 __device__ inline uint32_t row_bit(const uint32_t* row, int v) { return (row[v >> 5] >> (v & 31)) & 1u; }
 
 constexpr int FINE_BINS = 65536;
@@ -58,14 +51,20 @@ static_assert(FINE_BINS + COARSE_BINS == MERGE_HIST_INTS, "histogram layout");
 constexpr int MX_THREADS = 256;  // expand / count / scatter blocks
 constexpr int LOCAL_BINS = 1024;
 
-// C_i(b_j) for every level and candidate; the level's largest possible score
-// increment (max_j C_i(b_j) + its total back-edge weight); the histogram
-// cleared for level 2. One wave per level.
+// C_i(b_j) for every level and candidate; the number of valid candidates
+// (those before the first 0xFFFFFFFF of the row); the level's largest
+// possible score increment (max_j C_i(b_j) + its total back-edge weight); the
+// histogram cleared for level 2. One wave per level (K <= 64).
 __global__ void k_merge_intra(const MergeLevel* lv, const int32_t* intra, const uint32_t* cand, int K, int64_t* ccut,
-                              uint32_t* maxinc, int32_t* hist, int32_t* below)
+                              int32_t* lvk, uint32_t* maxinc, int32_t* hist, int32_t* below)
 {
     const int i = blockIdx.x;
     const MergeLevel& L = lv[i];
+    {
+        const int lane = threadIdx.x;
+        const uint64_t bad = __ballot(lane < K && cand[(size_t)i * K + lane] == 0xFFFFFFFFu);
+        if (lane == 0) lvk[i] = bad ? __ffsll((unsigned long long)bad) - 1 : K;
+    }
     int32_t best = 0;  // total weight < 2^31
     for (int j = threadIdx.x; j < K; j += blockDim.x) {
         const uint32_t b = cand[(size_t)i * K + j];
@@ -94,9 +93,9 @@ __global__ void k_merge_intra(const MergeLevel* lv, const int32_t* intra, const 
 }
 
 // level 1: the 2 K_1 paths (j, o) in order b_1, ~b_1, b_2, ~b_2, ...
-__global__ void k_merge_first(const uint32_t* cand, int K, const int64_t* ccut, uint32_t* keys, int32_t* npaths)
+__global__ void k_merge_first(const int32_t* lvk, int K, const int64_t* ccut, uint32_t* keys, int32_t* npaths)
 {
-    const int Kv = level_k(cand, K, 0);
+    const int Kv = lvk[0];
     for (int d = threadIdx.x; d < 2 * K; d += blockDim.x) {
         const int j = d >> 1;
         keys[d] = j < Kv ? (uint32_t)(ccut[j] + 1) : 0u;
@@ -410,15 +409,22 @@ __global__ void k_merge_build(const MergeLevel* lv, const uint32_t* cand, const 
 // of two; thread t is child j = t % Kp of local parent t / Kp (j >= K idle),
 // so a parent's children are consecutive lanes of one wave.
 
+constexpr int EDGE_STAGE = 2048;  // back edges staged in LDS per round
+constexpr int ROW_STAGE = 4096;   // row words staged in LDS (else read from memory)
+
 __global__ __launch_bounds__(MX_THREADS) void k_merge_expand(const MergeLevel* lv, int i, const int32_t* back,
                                                              const uint32_t* cand, int K, int lgKp,
-                                                             const int64_t* ccut, const uint32_t* rows, int nw,
-                                                             const int64_t* scores, const int32_t* npaths,
-                                                             const MergeLvState* lvs, const uint32_t* maxinc,
-                                                             uint32_t* keys, int32_t* hist, int32_t* below)
+                                                             const int64_t* ccut, const int32_t* lvk,
+                                                             const uint32_t* rows, int nw, const int64_t* scores,
+                                                             const int32_t* npaths, const MergeLvState* lvs,
+                                                             const uint32_t* maxinc, uint32_t* keys, int32_t* hist,
+                                                             int32_t* below)
 {
     __shared__ int32_t A[MX_THREADS][32];
     __shared__ int32_t lh[LOCAL_BINS];
+    __shared__ int32_t se_u[EDGE_STAGE], se_w[EDGE_STAGE];
+    __shared__ uint32_t srow[ROW_STAGE];
+    __shared__ int32_t s_kbeg[33];
     __shared__ uint32_t s_dmin;
     const int t = threadIdx.x;
     const int PPB = MX_THREADS >> lgKp;
@@ -428,39 +434,70 @@ __global__ __launch_bounds__(MX_THREADS) void k_merge_expand(const MergeLevel* l
     if (p0 >= np) return;  // uniform
     const int nact = np - p0 < PPB ? np - p0 : PPB;
     const MergeLevel& L = lv[i];
-    for (int x = t; x < nact * 32; x += MX_THREADS) A[x >> 5][x & 31] = 0;
-    for (int x = t; x < LOCAL_BINS; x += MX_THREADS) lh[x] = 0;
-    if (t == 0) s_dmin = 0xFFFFFFFFu;
-    __syncthreads();
-    // back-edge weights A_k of every parent of the block: (parent, edge)
-    // pairs spread over the lanes; integer sums, order-free
-    const int nb = L.kbeg[32];
-    for (int x = t; x < nact * nb; x += MX_THREADS) {
-        const int q = x / nb, e = x - q * nb;
-        const int32_t* E = back + 3 * (size_t)(L.back_off + e);
-        if (row_bit(rows + (size_t)(p0 + q) * nw, E[0])) atomicAdd(&A[q][E[1]], E[2]);
-    }
-    __syncthreads();
     const int p = p0 + pl;
-    uint32_t key = 0;
-    if (pl < nact && j < K) {
-        const int Kv = level_k(cand, K, i);
-        if (j < Kv) {
-            const uint32_t* row = rows + (size_t)p * nw;
-            const uint32_t b = cand[(size_t)i * K + j];
-            const uint32_t o = (b & 1u) ^ row_bit(row, L.start);
-            int64_t s = scores[p] + ccut[(size_t)i * K + j];
-            const int size = L.size;
-            for (int k = 1; k < size; ++k) {
-                const uint32_t y = ((b >> k) & 1u) ^ o;
-                s += y ? (L.wk[k] - (int64_t)A[pl][k]) : (int64_t)A[pl][k];
-            }
-            key = (uint32_t)(s + 1);
+    const bool mine = pl < nact && j < K;
+    // this child's inputs, loaded ahead of the staging
+    const uint32_t b = mine ? cand[(size_t)i * K + j] : 0u;
+    const int64_t base_score = mine ? scores[p] + ccut[(size_t)i * K + j] : 0;
+    const bool act = mine && j < lvk[i];
+    const uint32_t H = lvs[i - 1].best + maxinc[i];  // >= every key of the level
+    // rows of the block's parents up to the word of the shared vertex
+    const int wl = (L.start >> 5) + 1;
+    const bool rows_lds = nact * wl <= ROW_STAGE;
+    if (rows_lds)
+        for (int q = 0; q < nact; ++q)
+            for (int w = t; w < wl; w += MX_THREADS) srow[q * wl + w] = rows[(size_t)(p0 + q) * nw + w];
+    for (int x = t; x < LOCAL_BINS; x += MX_THREADS) lh[x] = 0;
+    for (int x = t; x < nact * 32; x += MX_THREADS) A[x >> 5][x & 31] = 0;
+    if (t < 33) s_kbeg[t] = L.kbeg[t];
+    if (t == 0) s_dmin = 0xFFFFFFFFu;
+    auto bit_of = [&](int q, int v) -> uint32_t {
+        return rows_lds ? (srow[q * wl + (v >> 5)] >> (v & 31)) & 1u : row_bit(rows + (size_t)(p0 + q) * nw, v);
+    };
+    // back-edge weights A_k of every parent: the thread that owns (q, k) sums
+    // the edges into local vertex k (sorted by k) whose earlier endpoint is 1
+    // in parent q
+    const int nb = L.kbeg[32];
+    for (int e0 = 0; e0 < nb || e0 == 0; e0 += EDGE_STAGE) {
+        const int ne = nb - e0 < EDGE_STAGE ? nb - e0 : EDGE_STAGE;
+        __syncthreads();  // the previous round's readers are done (first round: staging above is visible)
+        for (int x = t; x < ne; x += MX_THREADS) {
+            const int32_t* E = back + 3 * (size_t)(L.back_off + e0 + x);
+            se_u[x] = E[0];
+            se_w[x] = E[2];
         }
-        keys[(size_t)p * K + j] = key;
+        __syncthreads();
+        for (int x = t; x < nact * 32; x += MX_THREADS) {
+            const int q = x >> 5, k = x & 31;
+            const int lo = (s_kbeg[k] > e0 ? s_kbeg[k] : e0) - e0;
+            const int hi = (s_kbeg[k + 1] < e0 + ne ? s_kbeg[k + 1] : e0 + ne) - e0;
+            int32_t sum = 0;
+            int e = lo;
+            for (; e + 4 <= hi; e += 4) {  // four independent LDS chains in flight
+                const int u0 = se_u[e], u1 = se_u[e + 1], u2 = se_u[e + 2], u3 = se_u[e + 3];
+                const int32_t w0 = se_w[e], w1 = se_w[e + 1], w2 = se_w[e + 2], w3 = se_w[e + 3];
+                sum += (bit_of(q, u0) ? w0 : 0) + (bit_of(q, u1) ? w1 : 0) + (bit_of(q, u2) ? w2 : 0) +
+                       (bit_of(q, u3) ? w3 : 0);
+            }
+            for (; e < hi; ++e) sum += bit_of(q, se_u[e]) ? se_w[e] : 0;
+            A[q][k] += sum;  // (q, k) has one owner
+        }
+        if (nb == 0) break;
     }
-    // histogram of d = H - key (H >= every key of the level)
-    const uint32_t H = lvs[i - 1].best + maxinc[i];
+    __syncthreads();
+    uint32_t key = 0;
+    if (act) {
+        const uint32_t o = (b & 1u) ^ bit_of(pl, L.start);
+        int64_t s = base_score;
+        const int size = L.size;
+        for (int k = 1; k < size; ++k) {
+            const uint32_t y = ((b >> k) & 1u) ^ o;
+            s += y ? (L.wk[k] - (int64_t)A[pl][k]) : (int64_t)A[pl][k];
+        }
+        key = (uint32_t)(s + 1);
+    }
+    if (mine) keys[(size_t)p * K + j] = key;
+    // histogram of d = H - key
     const uint32_t d = H - key;
     const bool inwin = key != 0u && d < (uint32_t)FINE_BINS;
     const int32_t nbelow = wave_sum(key != 0u && !inwin);
@@ -623,32 +660,36 @@ __global__ __launch_bounds__(MX_THREADS) void k_merge_scatter(const MergeLevel* 
     const int p0 = blockIdx.x * PPB;
     const int np = npaths[i];
     if (p0 >= np) return;  // uniform
+    const int pl = t >> lgKp, j = t & ((1 << lgKp) - 1);
+    const int p = p0 + pl;
+    const MergeLevel& L = lv[i];
+    // independent loads first: this child's key, candidate and the parent's
+    // bit of the shared vertex, the threshold, the block's parent counts
+    const bool mine = p < np && j < K;
+    const uint32_t key = mine ? keys[(size_t)p * K + j] : 0u;
+    const uint32_t b = mine ? cand[(size_t)i * K + j] : 0u;
+    const uint32_t xs = mine ? row_bit(prow + (size_t)p * nw, L.start) : 0u;
     const uint32_t kstar = st->kstar;
     const int32_t R = st->R;
+    s_pc[t] = (t < PPB && p0 + t < np) ? pcnt[p0 + t] : 0;
+    if (t == 0) s_n = 0;
     // (gt, eq) counts of the parents before this block
     int64_t acc = 0;
     for (int x = t; x < p0; x += MX_THREADS) acc += pcnt[x];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) s_red[wv] = acc;
-    const int pl = t >> lgKp, j = t & ((1 << lgKp) - 1);
-    const int p = p0 + pl;
-    s_pc[t] = (t < PPB && p0 + t < np) ? pcnt[p0 + t] : 0;
-    if (t == 0) s_n = 0;
     __syncthreads();
     int64_t before = 0;
     for (int w = 0; w < MX_THREADS / 64; ++w) before += s_red[w];
     for (int q = 0; q < pl; ++q) before += s_pc[q];  // the block's earlier parents
-    const uint32_t key = (p < np && j < K) ? keys[(size_t)p * K + j] : 0u;
     const bool g = key > kstar, e = key != 0u && key == kstar;
     const uint64_t earlier = ((1ull << lane) - 1ull) & parent_lanes(lane, lgKp);
     const int32_t my_gt = (int32_t)(before & 0xFFFFFFFFll) + __popcll(__ballot(g) & earlier);
     const int32_t my_eq = (int32_t)(before >> 32) + __popcll(__ballot(e) & earlier);
-    const MergeLevel& L = lv[i];
     if (g || (e && my_eq < R)) {
         const int32_t pos = my_gt + (my_eq < R ? my_eq : R);
-        const uint32_t b = cand[(size_t)i * K + j];
-        const uint32_t o = (b & 1u) ^ row_bit(prow + (size_t)p * nw, L.start);
+        const uint32_t o = (b & 1u) ^ xs;
         const int slot = atomicAdd(&s_n, 1);
         s_pos[slot] = pos;
         s_src[slot] = p;
@@ -681,9 +722,9 @@ __global__ void k_merge_fail(uint32_t* out, int nw, int64_t* cut, const int32_t*
 hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV, const uint32_t* cand,
                         uint32_t* best, int64_t* best_cut, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_merge_intra, dim3(M), dim3(64), 0, s, m.lv, m.intra, cand, K, m.ccut, m.maxinc, m.hist,
-                       m.below);
-    hipLaunchKernelGGL(k_merge_first, dim3(1), dim3(128), 0, s, cand, K, m.ccut, m.keys, m.counts);
+    hipLaunchKernelGGL(k_merge_intra, dim3(M), dim3(64), 0, s, m.lv, m.intra, cand, K, m.ccut, m.lvk, m.maxinc,
+                       m.hist, m.below);
+    hipLaunchKernelGGL(k_merge_first, dim3(1), dim3(128), 0, s, m.lvk, K, m.ccut, m.keys, m.counts);
     // level 1: counts[0] = 1 path, counts[1] = its survivors
     const bool last0 = M == 1;
     hipLaunchKernelGGL(k_merge_select, dim3(1), dim3(SEL_THREADS), 0, s, m.keys, m.counts, 2 * K, last0 ? 1 : W,
@@ -698,7 +739,8 @@ hipError_t launch_merge(const MergeBufs& m, int M, int K, int W, int nw, int nV,
     for (int i = 1; i < M; ++i) {
         const bool last = i == M - 1;
         hipLaunchKernelGGL(k_merge_expand, dim3(nblk), dim3(MX_THREADS), 0, s, m.lv, i, m.back, cand, K, lgKp,
-                           m.ccut, m.rows[cur], nw, m.scores, m.counts, m.lvs, m.maxinc, m.keys, m.hist, m.below);
+                           m.ccut, m.lvk, m.rows[cur], nw, m.scores, m.counts, m.lvs, m.maxinc, m.keys, m.hist,
+                           m.below);
         hipLaunchKernelGGL(k_merge_count, dim3(nblk), dim3(MX_THREADS), 0, s, i, K, lgKp, m.counts + i,
                            last ? 1 : W, m.lvs + (i - 1), m.maxinc, m.keys, m.hist, m.below, m.pcnt, m.lvs + i,
                            m.counts + i + 1);

@@ -116,7 +116,15 @@ class Solver:
         self.step.zero_()
 
     def optimise(self, iters: int, stream=None):
-        """`iters` Adam ascent steps on every subgraph's <C> (no host sync)."""
+        """`iters` Adam ascent steps on every subgraph's <C>, one library call
+        (no host sync)."""
+        cfg = self.cfg
+        _abi.qaoa_optimize(self.batch.handle, cfg.p, iters, _ptr(self.theta), _ptr(self.m), _ptr(self.v),
+                           _ptr(self.step), cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, _ptr(self.E), _stream(stream))
+
+    def optimise_separate(self, iters: int, stream=None):
+        """The same steps as separate gradient and Adam calls (reference for
+        the fused path)."""
         cfg = self.cfg
         P = self.B * cfg.p
         s = _stream(stream)
@@ -128,16 +136,13 @@ class Solver:
 
     def _one_step(self, s: int):
         cfg = self.cfg
-        P = self.B * cfg.p
-        th, gr = _ptr(self.theta), _ptr(self.grad)
-        _abi.qaoa_expectation_grad(self.batch.handle, cfg.p, th, th + 8 * P, _ptr(self.E), gr, gr + 8 * P, s)
-        _abi.qaoa_adam_step(2 * P, th, gr, _ptr(self.m), _ptr(self.v), _ptr(self.step), cfg.lr, cfg.beta1,
-                            cfg.beta2, cfg.eps, 1, s)
+        _abi.qaoa_optimize(self.batch.handle, cfg.p, 1, _ptr(self.theta), _ptr(self.m), _ptr(self.v),
+                           _ptr(self.step), cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, _ptr(self.E), s)
 
     def optimise_graph(self, iters: int):
         """Same as `optimise`, replaying one captured HIP graph of an Adam step
-        (gradient kernels + Adam); the step counter lives on the device, so
-        every replay is the next step. The graph is captured on first use and
+        (angle tables, gradient passes, fused reduction + Adam); the step
+        counter lives on the device, so every replay is the next step. The graph is captured on first use and
         kept with the solver (it holds this batch's buffers)."""
         # the captured kernels reference only the workspace (whose layout a
         # rebuild of the same batch reproduces) and this solver's buffers

@@ -193,6 +193,30 @@ def test_plain_solve_400_vertices_full_size():
     S.close()
 
 
+@pytest.mark.parametrize("p_edge,skip", [(0.08, False), (0.03, True)])
+def test_fused_optimiser_matches_separate_calls(p_edge, skip):
+    """qaoa_optimize (one fused reduction + Adam + table kernel per step) gives
+    bit-identical angles, moments, step count and <C> to separate
+    qaoa_expectation_grad + qaoa_adam_step calls, on a ragged chain with
+    whole-state, one-group and two-group subgraphs (and edgeless ones skipped)."""
+    g = synth.erdos_renyi(120, p_edge, 5)
+    part = partition_chain(120, synth.ragged_sizes(6, 5, 23, 120))
+    cfg = SolveConfig(p=2, iters=7, k=8, beam=64)
+    S = Solver(g, part, cfg, skip_edgeless=skip)
+    g0, b0 = cold_start(cfg.p, part.M)
+    S.set_angles(g0, b0)
+    S.optimise_separate(7)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (S.theta, S.m, S.v, S.step, S.E)]
+    S.set_angles(g0, b0)
+    S.optimise(7)
+    torch.cuda.synchronize()
+    for name, a, b in zip(("theta", "m", "v", "step", "E"), ref, (S.theta, S.m, S.v, S.step, S.E)):
+        assert torch.equal(a, b), (name, int((a != b).sum()), float((a.double() - b.double()).abs().max()))
+    assert int(S.step.cpu()[0]) == 7
+    S.close()
+
+
 def test_graph_replay_matches_eager_optimiser():
     """A captured Adam step replayed T times gives bit-identical angles to T
     eager steps; replays are interleaved with eager work and checked each time."""
