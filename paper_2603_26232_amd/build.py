@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libparaqaoa.so")
-SOURCES = ["sim.hip", "topk.hip", "cut.hip", "merge.hip", "mlp.hip", "api.hip"]
+SOURCES = ["sim.hip", "optim.hip", "topk.hip", "cut.hip", "merge.hip", "mlp.hip", "api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -146,8 +146,6 @@ hipError_t launch_mlp_backward(int B, MlpDims d, const double* P, const float* X
 // ---- launchers (sim.hip) ----
 hipError_t launch_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork,
                              hipStream_t s);
-hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, const double* gamma,
-                             const double* beta, hipStream_t s);
 // chain: layout-chain code of the pass's group (3: group 0; 2 / 4: a high
 // group of 8 / 5..7 qubits; 1 / 5: a high group of 4 / 1..3 qubits)
 hipError_t launch_fwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, int chain,
@@ -156,6 +154,9 @@ hipError_t launch_bwd_pass(uint8_t* ws, const SubDesc* subs, const int2* work, i
                            PassOps ops, Partials part, int lut_max, hipStream_t s);
 hipError_t launch_small(uint8_t* ws, const SubDesc* subs, const int32_t* list, int nlist, int p,
                         int grad, Partials part, int lut_max, hipStream_t s);
+// ---- launchers (optim.hip) ----
+hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, const double* gamma,
+                             const double* beta, hipStream_t s);
 hipError_t launch_reduce(const SubDesc* subs, int B, int p, int grad, Partials part, double* E,
                          double* dgamma, double* dbeta, hipStream_t s);
 // ---- launchers (topk.hip) ----
@@ -165,6 +166,22 @@ hipError_t launch_topk(uint8_t* ws, const SubDesc* subs, const int2* work, int n
 hipError_t launch_maxcut_eval(int32_t nV, int64_t nE, const int32_t* u, const int32_t* v,
                               const int32_t* w, int64_t A, const uint32_t* assign, int64_t* cut,
                               hipStream_t s);
+// deterministic block sum of one double per thread: wave tree, then the
+// waves in order (thread 0 holds the result; blockDim a multiple of 64)
+__device__ inline double block_sum(double x, double* red)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    const uint32_t tid = threadIdx.x;
+    if ((tid & 63u) == 0) red[tid >> 6] = x;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0) {
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
 // Adam (Kingma and Ba 2015) update of one parameter in FP64 with the bias
 // corrections c1 = 1 - b1^t, c2 = 1 - b2^t; sign +1 ascends. The standalone
 // step and the fused optimiser kernel share it; every operation is an
@@ -182,7 +199,7 @@ __device__ __noinline__ inline void adam_update(double& th, double& m, double& v
     th = __dadd_rn(th, step);
 }
 // reduction of the gradient, Adam ascent step and the next step's tables,
-// one block per (subgraph, layer) (sim.hip)
+// one block per (subgraph, layer) (optim.hip)
 hipError_t launch_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p, Partials part, double* theta,
                               double* m, double* v, int32_t* step, int32_t* arrive, double lr, double b1, double b2,
                               double eps, double* E, hipStream_t s);

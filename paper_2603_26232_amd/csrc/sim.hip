@@ -529,20 +529,6 @@ __device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Ge
 }
 
 // deterministic block sum (wave64 butterfly, then the 4 wave totals in order)
-__device__ inline double block_sum(double x, double* red)
-{
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-    const uint32_t tid = threadIdx.x;
-    if ((tid & 63u) == 0) red[tid >> 6] = x;
-    __syncthreads();
-    double s = 0.0;
-    if (tid == 0) {
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-    }
-    __syncthreads();
-    return s;
-}
-
 // three deterministic block sums with one barrier pair
 __device__ inline void block_sum3(double& a, double& b, double& c, double* red)
 {
@@ -665,70 +651,6 @@ __global__ __launch_bounds__(THREADS) void k_cut_tables(uint8_t* ws, const SubDe
             else ((uint16_t*)tab)[q] = (uint16_t)c;
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// K2: angle preparation. LUT[c] = e^{-i gamma c} from an FP64 product and
-// FP64 sine/cosine, rounded to complex64; the rotation parameters of the
-// layer in FP64, rounded to float.
-// ---------------------------------------------------------------------------
-__device__ inline void cpow_d(double re, double im, int e, double& ore, double& oim)
-{
-    double r = 1.0, i = 0.0;
-    for (int k = 0; k < e; ++k) {
-        const double nr = r * re - i * im, ni = r * im + i * re;
-        r = nr;
-        i = ni;
-    }
-    ore = r;
-    oim = i;
-}
-
-// entry c of layer l's phase table: e^{-i gamma c} (c = 0 .. weight sum).
-// This and prep_coef are compiled once (not inlined), so the standalone table
-// kernel and the fused optimiser kernel produce the same bits.
-__device__ __noinline__ void prep_lut_entry(uint8_t* ws, const SubDesc* sd, int l, int c, double gm)
-{
-    double sv, cv;
-    sincos(gm * (double)c, &sv, &cv);
-    ((float2*)(ws + sd->lut))[(size_t)l * sd->lut_len + c] = make_float2((float)cv, (float)(-sv));
-}
-
-// rotation parameters of layer l (one thread)
-__device__ __noinline__ void prep_coef(uint8_t* ws, const SubDesc* sd, int l, double bt)
-{
-    double s, c;
-    sincos(bt, &s, &c);
-    RxCoef rc;
-    rc.cs = make_float2((float)c, (float)s);
-    // e^{-i beta X} = c (I - i tan(beta) X)            when |cos| >= |sin|
-    //               = -i s X (I + i cot(beta) X)       otherwise
-    // i.e. f (I - i t X) X^flip with (f, t) = (c, tan) or (-i s, -cot)
-    const bool tanm = fabs(c) >= fabs(s);
-    rc.mode = tanm ? 0 : 1;
-    rc.t = (float)(tanm ? s / c : -c / s);
-    rc.fsq = (float)(tanm ? c * c : s * s);
-    // per-qubit factors: forward c or -i s, inverse c or +i s
-    const double fr = tanm ? c : 0.0, fi_f = tanm ? 0.0 : -s, fi_i = tanm ? 0.0 : s;
-    for (int g = 0; g < MAX_GROUPS; ++g) {
-        const int nq = g < sd->ngroups ? sd->gsize[g] : 0;
-        double r, i;
-        cpow_d(fr, fi_f, nq, r, i);
-        rc.Ff[g] = make_float2((float)r, (float)i);
-        cpow_d(fr, fi_i, nq, r, i);
-        rc.Fi[g] = make_float2((float)r, (float)i);
-    }
-    ((RxCoef*)(ws + sd->coef))[l] = rc;
-}
-
-__global__ __launch_bounds__(THREADS) void k_angle_prep(uint8_t* ws, const SubDesc* subs, int p,
-                                                        const double* gamma, const double* beta)
-{
-    const int b = blockIdx.x / p, l = blockIdx.x % p;
-    const SubDesc* sd = subs + b;
-    const double gm = gamma[(size_t)b * p + l];
-    for (int c = threadIdx.x; c < sd->lut_len; c += THREADS) prep_lut_entry(ws, sd, l, c, gm);
-    if (threadIdx.x == 0) prep_coef(ws, sd, l, beta[(size_t)b * p + l]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1091,139 +1013,12 @@ __global__ __launch_bounds__(THREADS) void k_small(uint8_t* ws, const SubDesc* s
 }
 
 // ---------------------------------------------------------------------------
-// K5: per-subgraph fixed-order reduction of the tile partials.
-// dE/dgamma = 2 sum gg, dE/dbeta = 2 sum gb (the factor 2 of 2 Im <.|.|.>).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(THREADS) void k_reduce(const SubDesc* subs, int p, int grad, Partials part,
-                                                    double* E, double* dgamma, double* dbeta)
-{
-    // block (b, q): q = 0 sums <C>, q = 1..p the gamma term of layer q - 1,
-    // q = p + 1..2p the beta terms of layer q - p - 1 (over every group)
-    __shared__ double red[THREADS / 64];
-    const int b = blockIdx.x, q = blockIdx.y;
-    const SubDesc* sd = subs + b;
-    const int T = part.total_tiles, tb = sd->tile_base, nt = sd->ntiles, G = sd->ngroups;
-    double acc = 0.0;
-    if (q == 0) {
-        for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.e[tb + i];
-    } else if (q <= p) {
-        for (int i = threadIdx.x; i < nt; i += THREADS) acc += part.gg[(size_t)(q - 1) * T + tb + i];
-    } else {
-        const int l = q - p - 1;
-        for (int i = threadIdx.x; i < nt; i += THREADS)
-            for (int g = 0; g < G; ++g) acc += part.gb[((size_t)l * MAX_GROUPS + g) * T + tb + i];
-    }
-    acc = block_sum(acc, red);
-    if (threadIdx.x == 0) {
-        if (q == 0) {
-            if (E) E[b] = acc;
-        } else if (q <= p) {
-            dgamma[(size_t)b * p + q - 1] = 2.0 * acc;
-        } else {
-            dbeta[(size_t)b * p + q - p - 1] = 2.0 * acc;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One step of the angle optimisation after its gradient passes. Block
-// (b, l) owns layer l of subgraph b: it sums the tile partials of dE/dgamma_l
-// and dE/dbeta_l (and of <C> for l = 0) exactly as k_reduce does, takes the
-// Adam ascent step on gamma_l and beta_l (theta = [gamma of every subgraph |
-// beta of every subgraph]) as k_adam does, and prepares the phase table and
-// rotation parameters of the new angles as k_angle_prep does. The step count
-// is read by every block; the last block to arrive (a counter, no waiting)
-// advances it and clears the counter.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p,
-                                                         Partials part, double* theta, double* m, double* v,
-                                                         int32_t* step, int32_t* arrive, double lr, double b1,
-                                                         double b2, double eps, double* E)
-{
-    constexpr int NW = THREADS / 64;
-    __shared__ double red[3][NW];
-    __shared__ double s_gamma;
-    __shared__ int32_t s_last;
-    const int b = blockIdx.x / p, l = blockIdx.x % p;
-    const SubDesc* sd = subs + b;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int32_t t = *step + 1;
-    const int T = part.total_tiles, tb = sd->tile_base, nt = sd->ntiles, G = sd->ngroups;
-    // sums (k_reduce's terms and order: per thread in tile order, groups
-    // inner; the wave tree; the waves in order): 0 = dE/dgamma_l,
-    // 1 = dE/dbeta_l, 2 = <C>
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
-    for (int i = threadIdx.x; i < nt; i += THREADS) {
-        x0 += part.gg[(size_t)l * T + tb + i];
-        for (int g = 0; g < G; ++g) x1 += part.gb[((size_t)l * MAX_GROUPS + g) * T + tb + i];
-        if (l == 0) x2 += part.e[tb + i];
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        x0 += __shfl_xor(x0, off);
-        x1 += __shfl_xor(x1, off);
-        x2 += __shfl_xor(x2, off);
-    }
-    if (lane == 0) {
-        red[0][wv] = x0;
-        red[1][wv] = x1;
-        red[2][wv] = x2;
-    }
-    // bias corrections while the sums complete
-    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        const int q = threadIdx.x;  // 0: gamma_l, 1: beta_l
-        double acc = 0.0;
-        for (int w = 0; w < NW; ++w) acc += red[q][w];
-        const size_t idx = (q == 0 ? 0 : (size_t)B * p) + (size_t)b * p + l;
-        double th = theta[idx], mi = m[idx], vi = v[idx];
-        adam_update(th, mi, vi, 2.0 * acc, c1, c2, lr, b1, b2, eps, 1.0);
-        m[idx] = mi;
-        v[idx] = vi;
-        theta[idx] = th;
-        if (q == 0) s_gamma = th;
-        else prep_coef(ws, sd, l, th);  // rotation parameters of the new beta_l
-    } else if (threadIdx.x == 64) {
-        __threadfence();  // this block's read of the step count is done
-        s_last = atomicAdd(arrive, 1) == (int)gridDim.x - 1;
-        if (l == 0 && E) {
-            double e = 0.0;
-            for (int w = 0; w < NW; ++w) e += red[2][w];
-            E[b] = e;
-        }
-    }
-    __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        *step = t;
-        *arrive = 0;
-    }
-    const double gm = s_gamma;
-    for (int c = threadIdx.x; c < sd->lut_len; c += THREADS) prep_lut_entry(ws, sd, l, c, gm);
-}
-
-// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p, Partials part, double* theta,
-                              double* m, double* v, int32_t* step, int32_t* arrive, double lr, double b1, double b2,
-                              double eps, double* E, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reduce_adam, dim3(B * p), dim3(THREADS), 0, s, ws, subs, B, p, part, theta, m, v, step,
-                       arrive, lr, b1, b2, eps, E);
-    return hipGetLastError();
-}
-
 hipError_t launch_cut_tables(uint8_t* ws, const SubDesc* subs, const int2* work, int nwork, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cut_tables, dim3(nwork), dim3(THREADS), 0, s, ws, subs, work);
-    return hipGetLastError();
-}
-
-hipError_t launch_angle_prep(uint8_t* ws, const SubDesc* subs, int B, int p, const double* gamma,
-                             const double* beta, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_angle_prep, dim3(B * p), dim3(THREADS), 0, s, ws, subs, p, gamma, beta);
     return hipGetLastError();
 }
 
@@ -1310,14 +1105,6 @@ hipError_t launch_small(uint8_t* ws, const SubDesc* subs, const int32_t* list, i
     if (nlist <= 0) return hipSuccess;
     const size_t lds = (size_t)((grad ? 2 : 1) * TILE + lut_max) * sizeof(float2);
     hipLaunchKernelGGL(k_small, dim3(nlist), dim3(THREADS), lds, s, ws, subs, list, p, grad, part);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(const SubDesc* subs, int B, int p, int grad, Partials part, double* E,
-                         double* dgamma, double* dbeta, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reduce, dim3(B, grad ? 1 + 2 * p : 1), dim3(THREADS), 0, s, subs, p, grad, part, E, dgamma,
-                       dbeta);
     return hipGetLastError();
 }
 
