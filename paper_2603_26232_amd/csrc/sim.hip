@@ -808,17 +808,19 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
         for (int i = tid; i < lut_len; i += THREADS) lut[i] = L[i];
     }
+    // the cut values (used after the first segment) are loaded with the
+    // states, so their latency is hidden behind that segment
+    uint16_t cr[REGS];
+    if constexpr (KIND != B_SINGLE) load_cut_L<LE>(cr, tab, tid, m_pre);
     float2 ps[REGS], la[REGS];
     if constexpr (KIND != B_LAST) load_state<LS, CH == 3>(ps, sp, geo, tid);
     if constexpr (KIND != B_FUSED) load_state<LS, CH == 3>(la, sl, geo, tid);
     __syncthreads();
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
-    uint16_t cr[REGS];
     if constexpr (KIND == B_LAST) {
         // lambda back through RX(pre); slot q then holds amplitude q ^ m_pre
         seg_rot<CH, FULL, true>(la, lds, geo.c, -pre.t, tid);
         scale_regs(la, pre.Fi);
-        load_cut_L<LE>(cr, tab, tid, m_pre);
         const float amp = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
         float a = 0.f;
 #pragma unroll
@@ -835,7 +837,6 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
         // psi_p = RX(pre) psi (slot q then holds amplitude q ^ m_pre)
         seg_rot<CH, FULL, true>(ps, lds, geo.c, pre.t, tid);
         scale_regs(ps, pre.Ff);
-        load_cut_L<LE>(cr, tab, tid, m_pre);
 #pragma unroll
         for (int r = 0; r < REGS; ++r) {
             const float c = (float)cr[r];
@@ -851,7 +852,6 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_
             scale_regs(ps, pre.Fi);
             scale_regs(la, pre.Fi);
         } else {
-            load_cut_L<LE>(cr, tab, tid, m_pre);
             // on the rotated-but-unscaled states; rescale by |F|^2
             float a = 0.f;
 #pragma unroll

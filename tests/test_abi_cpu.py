@@ -88,11 +88,27 @@ def test_create_validates_edges_before_any_device_work():
 
 def test_calls_on_null_handle_are_rejected():
     for fn, args in [(_abi.qaoa_apply_layers, (0, 1, 8, 8, 0)), (_abi.qaoa_expectation, (0, 8, 0)),
-                     (_abi.qaoa_topk, (0, 4, 8, 8, 0))]:
+                     (_abi.qaoa_topk, (0, 4, 8, 8, 0)),
+                     (_abi.qaoa_expectation_grad, (0, 1, 8, 8, 8, 8, 8, 0)),
+                     (_abi.qaoa_optimize, (0, 1, 5, 8, 8, 8, 8, 0.05, 0.9, 0.999, 1e-8, 0, 0))]:
         with pytest.raises(_abi.QaoaError) as ei:
             fn(*args)
         assert ei.value.status == 1
     _abi.qaoa_batch_destroy(0)  # NULL is accepted
+
+
+def test_adam_arguments_are_checked_on_the_host():
+    # (count, theta, grad, m, v, step, lr, beta1, beta2, eps): status
+    cases = [((0, 8, 8, 8, 8, 8, 0.05, 0.9, 0.999, 1e-8), 1),
+             ((4, 0, 8, 8, 8, 8, 0.05, 0.9, 0.999, 1e-8), 1),
+             ((4, 8, 8, 8, 8, 0, 0.05, 0.9, 0.999, 1e-8), 1),
+             ((4, 8, 8, 8, 8, 8, 0.05, 1.0, 0.999, 1e-8), 2),
+             ((4, 8, 8, 8, 8, 8, 0.05, 0.9, 0.999, 0.0), 2),
+             ((4, 8, 8, 8, 8, 8, -1.0, 0.9, 0.999, 1e-8), 2)]
+    for args, status in cases:
+        with pytest.raises(_abi.QaoaError) as ei:
+            _abi.qaoa_adam_step(*args, 1, 0)
+        assert ei.value.status == status, args
 
 
 # ---------------------------------------------------------------- host prep
