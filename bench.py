@@ -7,7 +7,9 @@ subgraph's angles on exact adjoint gradients, the final state and <C>, top-16
 extraction, the level-wise beam merge (W = 4096) and the integer CutVal of the
 winner. Erdos-Renyi G(400, 0.05), seed 0, unit weights, partitioned into 21
 chained subgraphs of 20 vertices (20 qubits, 2^20 complex64 amplitudes each),
-QAOA depth p = 3.
+QAOA depth p = 3. Consecutive solves are pipelined: a solve's merge and CutVal
+run on a second stream while the next solve starts (--no-overlap runs them in
+line); the timed region still ends when every solve's merge has finished.
 
 Other workloads (--workload):
   ragged2000   the same solve on G(2000, 0.01), seed 0, a chain of ragged
@@ -101,7 +103,7 @@ def workload_solve(args, name):
 
     def step():
         S.rebuild()
-        S.run(graph=args.graph)
+        S.run(graph=args.graph, overlap=not args.no_overlap)
 
     def summary():
         r = S.result()
@@ -129,7 +131,8 @@ def workload_solve(args, name):
                 "sample": f"{len(idx)} subgraphs ({which}) of this workload, {T} Adam steps with adjoint "
                           f"gradients + final evaluation and top-{cfg.k} (FP64)"}
 
-    config = {"workload": desc, "graph_replay": bool(args.graph), "vertices": g.num_vertices, "edges": g.num_edges,
+    config = {"workload": desc, "graph_replay": bool(args.graph), "merge_overlaps_next_solve": not args.no_overlap,
+              "vertices": g.num_vertices, "edges": g.num_edges,
               "subgraphs": part.M, "simulated_subgraphs": len(sim),
               "qubits": [int(min(part.size)), int(max(part.size))],
               "p": cfg.p, "adam_steps": cfg.iters, "k": cfg.k, "beam": cfg.beam}
@@ -187,6 +190,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["plain400", "ragged2000", "precision26"], default="plain400")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run each solve's merge on the main stream instead of overlapping it with the next solve")
     ap.add_argument("--mixer", choices=["valu", "mfma_f32", "mfma_bf16x3", "mfma_bf16x4"], default="valu",
                     help="mixer precision mode (precision26 only)")
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")

@@ -83,6 +83,12 @@ class Solver:
         self.eval_cut = torch.zeros(1, dtype=torch.int64, device=dev)
         mb = _abi.qaoa_merge_workspace_bytes(graph.num_vertices, part.M, graph.num_edges, cfg.k, cfg.beam)
         self.merge_ws = torch.empty(mb, dtype=torch.uint8, device=dev)
+        # overlapped finish: a second merge slot, its stream and slot events
+        self._slot1 = None
+        self._side = None
+        self._slot_free = [None, None]
+        self._next_slot = 0
+        self._last_slot = 0
 
     def rebuild(self, stream=None):
         """Re-create the batch on its existing workspace: validates the
@@ -157,23 +163,54 @@ class Solver:
         for _ in range(iters):
             self._graph.replay()
 
-    def finish(self, stream=None):
-        """Final state, expectation, top-k, merge and CutVal (device only)."""
+    def _merge_slot(self, k):
+        """Buffers of merge slot k: (idx, prob, merge_ws, best, best_cut, eval_cut)."""
+        if k == 0:
+            return self.idx, self.prob, self.merge_ws, self.best, self.best_cut, self.eval_cut
+        if self._slot1 is None:
+            self._slot1 = tuple(torch.empty_like(t) for t in self._merge_slot(0))
+        return self._slot1
+
+    def finish(self, stream=None, overlap=False):
+        """Final state, expectation, top-k, merge and CutVal (device only).
+
+        overlap: run the merge and CutVal on a second stream (default
+        priority) so that they overlap whatever the caller enqueues next on
+        `stream` (the next solve); the two merge slots alternate, and a slot's
+        top-k waits until the merge that last read it has finished."""
         cfg = self.cfg
         P = self.B * cfg.p
-        s = _stream(stream)
+        main = stream if stream is not None else torch.cuda.current_stream()
+        s = int(main.cuda_stream)
+        k = self._next_slot if overlap else 0
+        idx, prob, mws, best, best_cut, eval_cut = self._merge_slot(k)
+        if overlap and self._slot_free[k] is not None:
+            main.wait_event(self._slot_free[k])
         th = _ptr(self.theta)
         _abi.qaoa_apply_layers(self.batch.handle, cfg.p, th, th + 8 * P, s)
         _abi.qaoa_expectation(self.batch.handle, _ptr(self.E), s)
-        _abi.qaoa_topk(self.batch.handle, cfg.k, _ptr(self.idx), _ptr(self.prob), s)
+        _abi.qaoa_topk(self.batch.handle, cfg.k, _ptr(idx), _ptr(prob), s)
+        ms = s
+        if overlap:
+            if self._side is None:
+                self._side = torch.cuda.Stream()
+            ready = torch.cuda.Event()
+            ready.record(main)
+            self._side.wait_event(ready)
+            ms = int(self._side.cuda_stream)
         g = self.g
         _abi.qaoa_merge_beam(g.num_vertices, self.part.M, self.part.start, self.part.size, g.num_edges, g.u, g.v,
-                             g.w, cfg.k, _ptr(self.idx), cfg.beam, _ptr(self.merge_ws), self.merge_ws.numel(),
-                             _ptr(self.best), _ptr(self.best_cut), s)
-        _abi.maxcut_eval(g.num_vertices, g.num_edges, _ptr(self.du), _ptr(self.dv), _ptr(self.dw), 1,
-                         _ptr(self.best), _ptr(self.eval_cut), s)
+                             g.w, cfg.k, _ptr(idx), cfg.beam, _ptr(mws), mws.numel(), _ptr(best), _ptr(best_cut), ms)
+        _abi.maxcut_eval(g.num_vertices, g.num_edges, _ptr(self.du), _ptr(self.dv), _ptr(self.dw), 1, _ptr(best),
+                         _ptr(eval_cut), ms)
+        if overlap:
+            done = torch.cuda.Event()
+            done.record(self._side)
+            self._slot_free[k] = done
+            self._next_slot ^= 1
+        self._last_slot = k
 
-    def run(self, gamma0=None, beta0=None, iters=None, stream=None, graph=False):
+    def run(self, gamma0=None, beta0=None, iters=None, stream=None, graph=False, overlap=False):
         if gamma0 is None:
             gamma0, beta0 = cold_start(self.cfg.p, self.B)
         self.set_angles(gamma0, beta0)
@@ -182,20 +219,22 @@ class Solver:
             self.optimise_graph(n)
         else:
             self.optimise(n, stream)
-        self.finish(stream)
+        self.finish(stream, overlap=overlap)
 
     def result(self) -> SolveResult:
+        """The last finished solve's outputs (waits for the device)."""
         torch.cuda.synchronize()
+        idx, _, _, best, best_cut, eval_cut = self._merge_slot(self._last_slot)
         P = self.B * self.cfg.p
         th = self.theta.cpu().numpy()
-        words = self.best.cpu().numpy().view(np.uint32)
+        words = best.cpu().numpy().view(np.uint32)
         nV = self.g.num_vertices
         x = ((words[np.arange(nV) // 32] >> (np.arange(nV) % 32).astype(np.uint32)) & 1).astype(np.uint8)
-        cut = int(self.eval_cut.cpu()[0])
-        assert cut == int(self.best_cut.cpu()[0]), "merge score and CutVal disagree"
+        cut = int(eval_cut.cpu()[0])
+        assert cut == int(best_cut.cpu()[0]), "merge score and CutVal disagree"
         return SolveResult(cut=cut, assignment=x, energies=self.E.cpu().numpy(),
                            gamma=th[:P].reshape(self.B, -1), beta=th[P:].reshape(self.B, -1),
-                           cand=self.idx.cpu().numpy().view(np.uint32).reshape(self.B, -1))
+                           cand=idx.cpu().numpy().view(np.uint32).reshape(self.B, -1))
 
     def close(self):
         self.batch.close()

@@ -238,3 +238,22 @@ def test_graph_replay_matches_eager_optimiser():
         S.finish()
         torch.cuda.synchronize()
     S.close()
+
+
+def test_overlapped_merge_matches_in_line_solves():
+    """Solves whose merge runs on a second stream while the next solve starts
+    (two alternating merge slots) give the same results as in-line solves."""
+    g = synth.erdos_renyi(140, 0.08, 3)
+    part = partition_equal(140, 14)
+    cfg = SolveConfig(p=2, iters=4, k=8, beam=256)
+    S = Solver(g, part, cfg)
+    S.run()
+    ref = S.result()
+    for _ in range(3):  # back to back: solve i's merge overlaps solve i + 1
+        S.rebuild()
+        S.run(overlap=True)
+    got = S.result()
+    assert got.cut == ref.cut
+    assert np.array_equal(got.assignment, ref.assignment)
+    assert np.array_equal(got.cand, ref.cand)
+    S.close()
