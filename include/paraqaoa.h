@@ -113,8 +113,10 @@ qaoa_status_t qaoa_workspace_bytes(int32_t B, const int32_t* num_qubits, const i
  *   edge_w         host weights >= 0 or NULL (unit); per-subgraph sum <= 2047
  *   d_workspace    device buffer of at least qaoa_workspace_bytes bytes,
  *                  256-byte aligned; it must outlive the handle
- *   stream         the copy and the table build run on it; the call waits for
- *                  the host-to-device copy before returning
+ *   stream         the upload of the metadata and the table build are
+ *                  enqueued on it (after its earlier work); the host arrays
+ *                  are copied to pinned staging memory before the call
+ *                  returns, so they may be reused at once
  *   out            receives the handle (free it with qaoa_batch_destroy) */
 qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits, const int64_t* edge_offsets,
                                 const int32_t* edge_u, const int32_t* edge_v, const int32_t* edge_w,
@@ -122,7 +124,9 @@ qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits, const int6
                                 size_t workspace_bytes, qaoa_stream_t stream, qaoa_batch_t* out);
 
 /* Free the host metadata of a handle. NULL is accepted. Caller memory is
- * untouched; pending work on the handle's workspace must have finished. */
+ * untouched; work already enqueued for the handle keeps running (it reads
+ * only the workspace), so a new batch may be created on the same workspace
+ * and stream right away. */
 qaoa_status_t qaoa_batch_destroy(qaoa_batch_t h);
 
 /* The QAOA ansatz (Sec. 2.2): reset every subgraph's state to |+>^n and apply
@@ -243,7 +247,8 @@ qaoa_status_t qaoa_merge_workspace_bytes(int32_t num_vertices, int32_t M, int64_
  *                    (vertex t = word t/32, bit t%32; bit 1 = side S)
  *   d_best_cut       device int64 [1], its cut value; -1 (and a zero
  *                    assignment) if some row has no candidate
- * The host arrays are copied (the call waits for that copy). */
+ * The host arrays are copied to pinned staging memory before the call
+ * returns; the upload and the merge kernels are enqueued on `stream`. */
 qaoa_status_t qaoa_merge_beam(int32_t num_vertices, int32_t M, const int32_t* h_start, const int32_t* h_size,
                               int64_t num_edges, const int32_t* h_u, const int32_t* h_v, const int32_t* h_w,
                               int32_t K, const uint32_t* d_cand, int32_t W, void* d_workspace,

@@ -83,6 +83,8 @@ def _instance(seed, nV, N, K, raw=False, p_edge=0.1, weighted=False, ragged=Fals
     (7, 160, 8, 32, 8192, False, (1, 200000), False),
     (9, 160, 8, 32, 8192, True, False, True),
     (10, 200, 12, 64, 512, False, False, False),  # K = 64: a parent's children fill a wave
+    (12, 120, 10, 1, 300, False, True, False),    # K = 1: 256 parents per block, one lane each
+    (13, 25, 13, 6, 40, True, False, False),      # two levels: one multi-block level
 ])
 def test_merge_matches_oracle(seed, nV, N, K, W, raw, weighted, ragged):
     g, part, cand = _instance(seed, nV, N, K, raw=raw, weighted=weighted, ragged=ragged)
@@ -121,6 +123,17 @@ def test_merge_host_arrays_reusable_after_call():
     ref_cut, ref_x, _, _ = oracle.merge(g.num_vertices, part.start, part.size, g.u, g.v, g.w, cand, W=4096)
     assert int(cut.cpu()[0]) == ref_cut
     assert np.array_equal(_unpack(best.cpu().numpy(), g.num_vertices), ref_x)
+
+
+def test_merge_with_an_empty_level_reports_no_assignment():
+    """A level without candidates leaves no path: best cut -1, zero row."""
+    g, part, cand = _instance(14, 120, 10, 8)
+    cand[part.M // 2, :] = 0xFFFFFFFF
+    best, cut, _ = merge_beam(g, part, torch.as_tensor(cand.view(np.int32), device="cuda"), 8, 256)
+    assert int(cut.cpu()[0]) == -1
+    assert not best.cpu().numpy().any()
+    with pytest.raises(ValueError):
+        oracle.merge(g.num_vertices, part.start, part.size, g.u, g.v, g.w, cand, W=256)
 
 
 def test_merge_rejects_bad_chains():
