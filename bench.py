@@ -48,11 +48,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_record(kernel, workload):
-    """Measured HBM traffic per launch of `kernel` from the committed PMC
-    summary of the workload, if it was taken on the current kernel source;
-    else None."""
-    path = os.path.join(ROOT, "profiles", f"pmc_passes_{workload}.txt")
+def _record(path, kernel):
+    """The RECORD line of `kernel` in a committed profile summary, if that
+    summary was taken on the current kernel source; else None."""
     if not os.path.exists(path):
         return None
     rec = None
@@ -68,6 +66,21 @@ def traffic_record(kernel, workload):
     if sha != rec.get("source_sha256"):
         return None
     return rec
+
+
+def traffic_record(kernel, workload):
+    """Measured HBM traffic per launch of `kernel` (FETCH_SIZE + WRITE_SIZE)."""
+    return _record(os.path.join(ROOT, "profiles", f"pmc_passes_{workload}.txt"), kernel)
+
+
+def valu_record(kernel, workload):
+    """Measured wave-wide VALU instructions per launch of `kernel` (SQ_INSTS_VALU)."""
+    return _record(os.path.join(ROOT, "profiles", f"pmc_valu_{workload}.txt"), kernel)
+
+
+# wave-wide VALU instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+# per wave-wide FP32 instruction (16 lanes per cycle; no packed FP32)
+VALU_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def amp_updates(sizes, p):
@@ -295,6 +308,13 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "algo_bytes_per_launch": d["algo_bytes"] / d["launches"], "avg_launch_us": round(d["avg_us"], 2),
                 "traffic": (None if tr is None else tr["hbm_bytes_per_launch"])}
+    vr = valu_record(dom, args.workload) if args.mixer == "valu" else None
+    if vr is not None:
+        # the same kernel seen from the vector units: measured VALU issue rate
+        va = vr["valu_insts_per_launch"] / (d["avg_us"] * 1e-6)
+        roofline["alu"] = {"achieved": round(va / 1e9, 1), "peak": round(VALU_PEAK / 1e9, 1),
+                           "unit": "G VALU wave-instructions/s", "frac": round(va / VALU_PEAK, 4),
+                           "valu_insts_per_launch": vr["valu_insts_per_launch"]}
 
     out = {
         "metric": METRIC, "value": value, "unit": "amp-updates/s", "n_gpus": 1, "steps": args.steps,

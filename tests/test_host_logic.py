@@ -48,3 +48,24 @@ def test_traffic_record_lookup(tmp_path, monkeypatch):
     assert bench.traffic_record("fwd_mid_g1", "plain400") is None  # taken on another source
     assert bench.traffic_record("bwd_last_g0", "plain400") is None  # no record
     assert bench.traffic_record("bwd_mid_g0", "ragged2000") is None  # no file
+
+
+def test_valu_record_lookup(tmp_path, monkeypatch):
+    import hashlib
+    import bench
+    src = os.path.join(ROOT, "paper_2603_26232_amd", "csrc", "sim.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    recs = [{"kernel": "bwd_mid_g0", "source": "sim.hip", "source_sha256": sha, "valu_insts_per_launch": 99},
+            {"kernel": "fwd_mid_g0", "source": "sim.hip", "source_sha256": "f" * 64, "valu_insts_per_launch": 5}]
+    (prof / "pmc_valu_plain400.txt").write_text("header line\n" + "\n".join("RECORD " + json.dumps(r) for r in recs) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "paper_2603_26232_amd" / "csrc").mkdir(parents=True)
+    (tmp_path / "paper_2603_26232_amd" / "csrc" / "sim.hip").write_bytes(open(src, "rb").read())
+    assert bench.valu_record("bwd_mid_g0", "plain400")["valu_insts_per_launch"] == 99
+    assert bench.valu_record("fwd_mid_g0", "plain400") is None
+    assert bench.traffic_record("bwd_mid_g0", "plain400") is None  # the VALU file is not the traffic file
+    # the issue peak follows from the unit counts and clock
+    assert bench.VALU_PEAK == 614.4e9
+
