@@ -123,7 +123,7 @@ __global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubD
 {
     constexpr int NW = THREADS / 64;
     __shared__ double red[3][NW];
-    __shared__ double s_gamma;
+    __shared__ double s_gamma, s_beta;
     __shared__ int32_t s_last;
     const int b = blockIdx.x / p, l = blockIdx.x % p;
     const SubDesc* sd = subs + b;
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubD
         v[idx] = vi;
         theta[idx] = th;
         if (q == 0) s_gamma = th;
-        else prep_coef(ws, sd, l, th);  // rotation parameters of the new beta_l
+        else s_beta = th;
     } else if (threadIdx.x == 64) {
         __threadfence();  // this block's read of the step count is done
         s_last = atomicAdd(arrive, 1) == (int)gridDim.x - 1;
@@ -178,6 +178,9 @@ __global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubD
         *step = t;
         *arrive = 0;
     }
+    // the new angles' tables: the rotation parameters on the last thread,
+    // beside the phase-table entries of the others
+    if (threadIdx.x == THREADS - 1) prep_coef(ws, sd, l, s_beta);
     const double gm = s_gamma;
     for (int c = threadIdx.x; c < sd->lut_len; c += THREADS) prep_lut_entry(ws, sd, l, c, gm);
 }

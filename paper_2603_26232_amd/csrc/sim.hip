@@ -143,13 +143,38 @@ __device__ inline void lds_read(const float2* lds, uint32_t tid, float2 (&v)[REG
     for (int r = 0; r < REGS; ++r) v[r] = p[lds_idx(reg_part<L>(r))];
 }
 
+// LL0 and LL1 place the same 1024 amplitudes in each wave (thread bits 6, 7
+// are tile bits 10, 11 in both), so an exchange between them stays inside the
+// wave and needs no workgroup barrier: the LDS performs one wave's operations
+// in the order the wave issues them, so it is enough that the compiler keeps
+// the reads after the writes and the next writes after the reads. Every other
+// exchange moves data between waves.
 template <int LF, int LT>
+__host__ __device__ constexpr bool wave_local()
+{
+    return (LF == LL0 && LT == LL1) || (LF == LL1 && LT == LL0);
+}
+
+__device__ inline void wave_lds_order() { asm volatile("" ::: "memory"); }
+
+// LEAD: a barrier before the writes, for a workgroup exchange that follows a
+// wave-local one (other waves may still read their slots). The chains only
+// leave LL0 for LLIN after arriving from LL1, hence the default.
+template <int LF, int LT, bool LEAD = (LF == LL0 && LT == LLIN)>
 __device__ inline void xchg(float2* lds, uint32_t tid, float2 (&v)[REGS])
 {
-    lds_write<LF>(lds, tid, v);
-    __syncthreads();
-    lds_read<LT>(lds, tid, v);
-    __syncthreads();
+    if constexpr (wave_local<LF, LT>()) {
+        lds_write<LF>(lds, tid, v);
+        wave_lds_order();
+        lds_read<LT>(lds, tid, v);
+        wave_lds_order();
+    } else {
+        if constexpr (LEAD) __syncthreads();
+        lds_write<LF>(lds, tid, v);
+        __syncthreads();
+        lds_read<LT>(lds, tid, v);
+        __syncthreads();
+    }
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -434,7 +459,7 @@ __device__ inline void seg_bwd(float2 (&ps)[REGS], float2 (&la)[REGS], float2* l
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, ps);
-            xchg<L1, L2>(lds, tid, la);
+            xchg<L1, L2, false>(lds, tid, la);
             bwd_round<L2, FULL>(ps, la, c, rc.t, rc.fsq, wdone, xacc);
         }
     }
@@ -468,7 +493,7 @@ __device__ inline void seg_xb(float2 (&ps)[REGS], float2 (&la)[REGS], float2* ld
         if constexpr (CH >= 3) {
             constexpr int L2 = ChainAt<CH, DIR ? 2 : 0>::L;
             xchg<L1, L2>(lds, tid, ps);
-            xchg<L1, L2>(lds, tid, la);
+            xchg<L1, L2, false>(lds, tid, la);
             xacc += (double)xb_round<L2, FULL>(ps, la, c);
         }
     }
@@ -768,8 +793,10 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_MF_W
 // ---------------------------------------------------------------------------
 enum { B_FUSED = 0, B_SINGLE = 1, B_MID = 2, B_LAST = 3 };
 
+// The fused kind on group 0 is held to four waves per SIMD (the most that
+// its LDS tile allows); left free, it takes 130 registers and runs three.
 template <int CH, bool FULL, int KIND, bool STORE_PSI = true>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PQ_BWD_WAVES))) void k_bwd_pass(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND == B_FUSED && CH == 3 ? 4 : PQ_BWD_WAVES))) void k_bwd_pass(
     uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
 {
     extern __shared__ float2 smem[];
