@@ -714,9 +714,11 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     const uint32_t m_end = m_pre ^ ((HAS_POST && post.flip) ? gb : 0u);      // after RX(post)
     uint16_t cr[REGS];
     if constexpr (HAS_PH) {
-        // phase table, with the factor of the segment before it folded in
+        // phase table, with the factors of the segments before and after it
+        // folded in (the rotations are linear, so the factor of the one after
+        // may be applied before it)
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
-        const float2 F = HAS_PRE ? pre.Ff : make_float2(1.f, 0.f);
+        const float2 F = HAS_PRE ? cmul(pre.Ff, post.Ff) : post.Ff;
         for (int i = tid; i < lut_len; i += THREADS) lut[i] = cmul(L[i], F);
         if constexpr (HAS_PRE) load_cut_L<LE>(cr, tab, tid, m_pre);
         else load_cut_L<LS>(cr, tab, tid, 0u);
@@ -740,7 +742,6 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
         for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
         // FIRST walks start -> end, MID walks back end -> start
         seg_rot<CH, FULL, KIND == F_FIRST, PREC>(v, lds, geo.c, post.t, tid);
-        scale_regs(v, post.Ff);
     }
     double acc = 0.0;
     if constexpr (KIND == F_LAST) {
@@ -824,11 +825,14 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
     const uint32_t m_pre = pre.flip ? gb : 0u;
     const uint32_t m_end = m_pre ^ ((KIND == B_MID && post.flip) ? gb : 0u);
     if constexpr (KIND == B_MID) {
-        // conjugate phase table with the inverse factor of the preceding segment
+        // conjugate phase table with the inverse factors of the segments
+        // before and after it (the one after scales the states it rotates,
+        // so its beta terms are divided by |F|^2 at the end)
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
+        const float2 F = cmul(pre.Fi, post.Fi);
         for (int i = tid; i < lut_len; i += THREADS) {
             const float2 e = L[i];
-            lut[i] = cmul(make_float2(e.x, -e.y), pre.Fi);
+            lut[i] = cmul(make_float2(e.x, -e.y), F);
         }
     } else if constexpr (KIND == B_LAST) {
         // the phase table of layer 1 as the forward pass used it
@@ -898,8 +902,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 seg_bwd<CH, FULL, false>(ps, la, lds, geo.c, post, tid, acc_post);
-                scale_regs(ps, post.Fi);
-                scale_regs(la, post.Fi);
+                acc_post /= (double)post.Fi.x * post.Fi.x + (double)post.Fi.y * post.Fi.y;
             }
         }
     }

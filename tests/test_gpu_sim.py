@@ -196,7 +196,7 @@ def test_topk(sizes, k, raw):
 
 
 @pytest.mark.parametrize("sizes,p,seed", [([6], 1, 0), ([12], 2, 1), ([13, 16], 3, 2), ([20], 3, 3),
-                                          ([21, 12, 7], 2, 4), ([22], 3, 5)])
+                                          ([21, 12, 7], 2, 4), ([22], 3, 5), ([20, 21], 4, 6)])
 def test_gradient(sizes, p, seed):
     edges = _subgraphs(sizes, 300 + seed, p_edge=0.3, weighted=seed % 2 == 1)
     gamma, beta = synth.uniform_angles(900 + seed, p, batch=len(sizes))
