@@ -858,9 +858,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
         for (int r = 0; r < REGS; ++r) {
             const float2 f = lut[cr[r]];
             ps[r] = make_float2(amp * f.x, amp * f.y);
-            const float c = (float)cr[r];
-            a = fmaf(c * la[r].x, ps[r].y, a);
-            a = fmaf(-c * la[r].y, ps[r].x, a);
+            // C(z) Im(conj(lambda) psi)
+            a = fmaf((float)cr[r], fmaf(la[r].x, ps[r].y, -la[r].y * ps[r].x), a);
         }
         acc_ph = (double)a;
         seg_xb<CH, FULL, false>(ps, la, lds, geo.c, tid, acc_pre);
@@ -887,9 +886,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
             float a = 0.f;
 #pragma unroll
             for (int r = 0; r < REGS; ++r) {
-                const float c = (float)cr[r];
-                a = fmaf(c * la[r].x, ps[r].y, a);
-                a = fmaf(-c * la[r].y, ps[r].x, a);
+                // C(z) Im(conj(lambda) psi)
+                a = fmaf((float)cr[r], fmaf(la[r].x, ps[r].y, -la[r].y * ps[r].x), a);
             }
             acc_ph = (double)a * (double)(pre.Fi.x * pre.Fi.x + pre.Fi.y * pre.Fi.y);
             if constexpr (KIND == B_MID) {
