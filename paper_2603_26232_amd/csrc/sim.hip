@@ -533,24 +533,49 @@ __device__ inline CutTab tile_tab(const uint8_t* ws, const SubDesc* sd, int g, c
     return CutTab{(g == 0 ? ws + sd->tab : ws + sd->tabB) + (size_t)t * TILE * w, w};
 }
 
-template <int L, bool G0>
+// OFF32: addresses as 32-bit byte offsets from the state's (uniform) base
+// (a stored state of n <= 30 qubits spans at most 2^29 amplitudes = 4 GiB).
+// The map is XOR-linear, so a register's offset is the lane's offset XOR a
+// per-register value that is uniform across the workgroup: one vector XOR
+// per access instead of an XOR and a 64-bit address add.
+__device__ inline const float2& at_off(const float2* st, uint32_t off)
+{
+    return *(const float2*)((const uint8_t*)st + off);
+}
+
+template <int L, bool G0, bool OFF32 = false>
 __device__ inline void load_state(float2 (&v)[REGS], const float2* st, const Geo& geo, uint32_t tid)
 {
-    const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid));
+    if constexpr (OFF32) {
+        uint32_t base = (geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid))) << 3;
+        asm volatile("" : "+v"(base));  // keeps the shift out of the per-register XOR
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) v[r] = st[base ^ gmapT<G0>(geo, reg_part<L>(r))];
+        for (int r = 0; r < REGS; ++r) v[r] = at_off(st, base ^ (gmapT<G0>(geo, reg_part<L>(r)) << 3));
+    } else {
+        const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid));
+#pragma unroll
+        for (int r = 0; r < REGS; ++r) v[r] = st[base ^ gmapT<G0>(geo, reg_part<L>(r))];
+    }
     __builtin_amdgcn_sched_barrier(0);
 }
 
 // store slot q to amplitude q ^ m (gmap is a bit deposit, so it commutes with xor)
-template <int L, bool G0>
+template <int L, bool G0, bool OFF32 = false>
 __device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Geo& geo, uint32_t tid, uint32_t m)
 {
     // address arithmetic stays here (hoisting it holds 2 VGPRs per register)
     __builtin_amdgcn_sched_barrier(0);
-    const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid)) ^ gmapT<G0>(geo, m);
+    if constexpr (OFF32) {
+        uint32_t base = (geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid)) ^ gmapT<G0>(geo, m)) << 3;
+        asm volatile("" : "+v"(base));
 #pragma unroll
-    for (int r = 0; r < REGS; ++r) st[base ^ gmapT<G0>(geo, reg_part<L>(r))] = v[r];
+        for (int r = 0; r < REGS; ++r)
+            const_cast<float2&>(at_off(st, base ^ (gmapT<G0>(geo, reg_part<L>(r)) << 3))) = v[r];
+    } else {
+        const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid)) ^ gmapT<G0>(geo, m);
+#pragma unroll
+        for (int r = 0; r < REGS; ++r) st[base ^ gmapT<G0>(geo, reg_part<L>(r))] = v[r];
+    }
 }
 
 // deterministic block sum (wave64 butterfly, then the 4 wave totals in order)
@@ -844,8 +869,10 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
     uint16_t cr[REGS];
     if constexpr (KIND != B_SINGLE) load_cut_L<LE>(cr, tab, tid, m_pre);
     float2 ps[REGS], la[REGS];
-    if constexpr (KIND != B_LAST) load_state<LS, CH == 3>(ps, sp, geo, tid);
-    if constexpr (KIND != B_FUSED) load_state<LS, CH == 3>(la, sl, geo, tid);
+    // the middle kind (the busiest vector units) uses the one-XOR offsets
+    constexpr bool O32 = KIND == B_MID;
+    if constexpr (KIND != B_LAST) load_state<LS, CH == 3, O32>(ps, sp, geo, tid);
+    if constexpr (KIND != B_FUSED) load_state<LS, CH == 3, O32>(la, sl, geo, tid);
     __syncthreads();
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
     if constexpr (KIND == B_LAST) {
@@ -911,8 +938,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
         if constexpr (STORE_PSI) store_state<LE, CH == 3>(ps, sp, geo, tid, m_end);
         store_state<LE, CH == 3>(la, sl, geo, tid, m_end);
     } else if constexpr (KIND == B_MID) {
-        if constexpr (STORE_PSI) store_state<LS, CH == 3>(ps, sp, geo, tid, m_end);
-        store_state<LS, CH == 3>(la, sl, geo, tid, m_end);
+        if constexpr (STORE_PSI) store_state<LS, CH == 3, true>(ps, sp, geo, tid, m_end);
+        store_state<LS, CH == 3, true>(la, sl, geo, tid, m_end);
     }
     // partial sums: (<C> or gamma, beta of pre, beta of post)
     double s0 = KIND == B_FUSED ? acc_e : acc_ph, s1 = acc_pre, s2 = acc_post;
