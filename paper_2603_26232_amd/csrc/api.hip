@@ -388,7 +388,6 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
         d.tab = region(dim * (uint64_t)d.tabw, 4096);
         d.tabB = d.ngroups >= 2 ? region(dim * (uint64_t)d.tabw, 4096) : 0;
     }
-    (void)eo;
     P.total = align_up(o, 4096);
     return ok();
 }

@@ -526,10 +526,9 @@ __device__ inline void load_cut_L(uint16_t (&cr)[REGS], const CutTab& tab, uint3
 
 // the tile's slice of the table: both tables are stored in tile order (group
 // 0's mirror-paired tiles and the last group's strided tiles)
-__device__ inline CutTab tile_tab(const uint8_t* ws, const SubDesc* sd, int g, const Geo& geo, uint32_t t)
+__device__ inline CutTab tile_tab(const uint8_t* ws, const SubDesc* sd, int g, uint32_t t)
 {
     const int w = sd->tabw;
-    (void)geo;
     return CutTab{(g == 0 ? ws + sd->tab : ws + sd->tabB) + (size_t)t * TILE * w, w};
 }
 
@@ -542,6 +541,7 @@ __device__ inline const float2& at_off(const float2* st, uint32_t off)
 {
     return *(const float2*)((const uint8_t*)st + off);
 }
+__device__ inline float2& at_off(float2* st, uint32_t off) { return *(float2*)((uint8_t*)st + off); }
 
 template <int L, bool G0, bool OFF32 = false>
 __device__ inline void load_state(float2 (&v)[REGS], const float2* st, const Geo& geo, uint32_t tid)
@@ -570,7 +570,7 @@ __device__ inline void store_state(const float2 (&v)[REGS], float2* st, const Ge
         asm volatile("" : "+v"(base));
 #pragma unroll
         for (int r = 0; r < REGS; ++r)
-            const_cast<float2&>(at_off(st, base ^ (gmapT<G0>(geo, reg_part<L>(r)) << 3))) = v[r];
+            at_off(st, base ^ (gmapT<G0>(geo, reg_part<L>(r)) << 3)) = v[r];
     } else {
         const uint32_t base = geo.zb ^ gmapT<G0>(geo, thread_part<L>(tid)) ^ gmapT<G0>(geo, m);
 #pragma unroll
@@ -730,7 +730,7 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     float2* st = (float2*)(ws + sd->psi);
     const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
     const int lut_len = sd->lut_len;
-    const CutTab tab = tile_tab(ws, sd, g, geo, t);
+    const CutTab tab = tile_tab(ws, sd, g, t);
     const uint32_t gb = group_bits(geo.c);
     RxC pre{}, post{};
     if constexpr (HAS_PRE) pre = load_rx(cf, ops.pre, g);
@@ -842,7 +842,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
     const int lut_len = sd->lut_len;
     const int T = part.total_tiles;
     const int tile = sd->tile_base + (int)t;
-    const CutTab tab = tile_tab(ws, sd, g, geo, t);
+    const CutTab tab = tile_tab(ws, sd, g, t);
     const uint32_t gb = group_bits(geo.c);
     const RxC pre = load_rx(cf, ops.pre, g);
     RxC post{};
