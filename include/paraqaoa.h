@@ -198,7 +198,9 @@ qaoa_status_t qaoa_adam_step(int32_t count, double* d_theta, const double* d_gra
  *   d_E        device double [B] receiving <C> at the angles each step
  *              starts from (the last step's remains), or NULL
  * The state is consumed (call qaoa_apply_layers before qaoa_topk). Calls on
- * one batch must not overlap (they share a counter in the workspace). */
+ * one batch must not overlap (they share the batch's states and partial
+ * sums). d_step is read by every step of the call and advanced once, after
+ * its last step. */
 qaoa_status_t qaoa_optimize(qaoa_batch_t h, int32_t p, int32_t iters, double* d_theta, double* d_m, double* d_v,
                             int32_t* d_step, double lr, double beta1, double beta2, double eps, double* d_E,
                             qaoa_stream_t stream);

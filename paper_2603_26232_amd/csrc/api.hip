@@ -196,7 +196,7 @@ struct Plan {
     int64_t total_edges = 0;
     int lut_max = 1;
     // region offsets
-    uint64_t o_subs = 0, o_work_all = 0, o_small = 0, o_edges = 0, o_sync = 0, o_coef = 0, o_lut = 0, o_pe = 0,
+    uint64_t o_subs = 0, o_work_all = 0, o_small = 0, o_edges = 0, o_coef = 0, o_lut = 0, o_pe = 0,
              o_pgb = 0,
              o_pgg = 0, o_keys = 0, total = 0;
     int nsmall = 0;
@@ -365,7 +365,6 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     for (auto& c : P.classes) c.o_work = region(sizeof(int2) * c.work.size(), 256);
     P.o_small = region(sizeof(int32_t) * (P.nsmall + 1), 256);
     P.o_edges = region(sizeof(int32_t) * 3 * (P.total_edges + 1), 256);
-    P.o_sync = region(256, 256);  // block-arrival counter of the fused optimiser kernel (uploaded as zero)
     P.o_coef = region(sizeof(RxCoef) * B * max_p, 256);
     uint64_t lut_total = 0;
     for (int b = 0; b < B; ++b) lut_total += (uint64_t)max_p * P.subs[b].lut_len;
@@ -811,9 +810,10 @@ extern "C" qaoa_status_t qaoa_optimize(qaoa_batch_t h, int32_t p, int32_t iters,
         if (s != QAOA_OK) return s;
         ProfScope ps("reduce_adam", st,
                      8.0 * P.total_tiles * (1.0 + p * (MAX_GROUPS + 1.0)) + 7.0 * 8.0 * 2.0 * BP + angle_bytes(P, p));
-        HIP_TRY(launch_reduce_adam(h->ws, h->d_subs, P.B, p, h->part, d_theta, d_m, d_v, d_step,
-                                   (int32_t*)(h->ws + P.o_sync), lr, beta1, beta2, eps, d_E, st));
+        HIP_TRY(launch_reduce_adam(h->ws, h->d_subs, P.B, p, h->part, d_theta, d_m, d_v, d_step, it, lr, beta1,
+                                   beta2, eps, d_E, st));
     }
+    HIP_TRY(launch_step_advance(d_step, iters, st));
     h->state_valid = false;
     h->e_valid = true;
     return ok();

@@ -201,8 +201,9 @@ __device__ __noinline__ inline void adam_update(double& th, double& m, double& v
 // reduction of the gradient, Adam ascent step and the next step's tables,
 // one block per (subgraph, layer) (optim.hip)
 hipError_t launch_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p, Partials part, double* theta,
-                              double* m, double* v, int32_t* step, int32_t* arrive, double lr, double b1, double b2,
-                              double eps, double* E, hipStream_t s);
+                              double* m, double* v, const int32_t* step, int32_t it, double lr, double b1,
+                              double b2, double eps, double* E, hipStream_t s);
+hipError_t launch_step_advance(int32_t* step, int32_t n, hipStream_t s);
 hipError_t launch_adam(int32_t count, double* theta, const double* grad, double* m, double* v,
                        int32_t* step, double lr, double b1, double b2, double eps, double sign,
                        hipStream_t s);

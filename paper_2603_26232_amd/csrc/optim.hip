@@ -112,23 +112,23 @@ __global__ __launch_bounds__(THREADS) void k_reduce(const SubDesc* subs, int p, 
 // and dE/dbeta_l (and of <C> for l = 0) exactly as k_reduce does, takes the
 // Adam ascent step on gamma_l and beta_l (theta = [gamma of every subgraph |
 // beta of every subgraph]) as k_adam does, and prepares the phase table and
-// rotation parameters of the new angles as k_angle_prep does. The step count
-// is read by every block; the last block to arrive (a counter, no waiting)
-// advances it and clears the counter.
+// rotation parameters of the new angles as k_angle_prep does. Step `it` of
+// a run reads the step count the run started from and takes step
+// count + it + 1; the count itself advances once, after the run's last step
+// (k_step_advance), so no block waits for or signals another.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p,
                                                          Partials part, double* theta, double* m, double* v,
-                                                         int32_t* step, int32_t* arrive, double lr, double b1,
+                                                         const int32_t* step, int32_t it, double lr, double b1,
                                                          double b2, double eps, double* E)
 {
     constexpr int NW = THREADS / 64;
     __shared__ double red[3][NW];
     __shared__ double s_gamma, s_beta;
-    __shared__ int32_t s_last;
     const int b = blockIdx.x / p, l = blockIdx.x % p;
     const SubDesc* sd = subs + b;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int32_t t = *step + 1;
+    const int32_t t = *step + it + 1;
     const int T = part.total_tiles, tb = sd->tile_base, nt = sd->ntiles, G = sd->ngroups;
     // sums (k_reduce's terms and order: per thread in tile order, groups
     // inner; the wave tree; the waves in order): 0 = dE/dgamma_l,
@@ -164,20 +164,12 @@ __global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubD
         theta[idx] = th;
         if (q == 0) s_gamma = th;
         else s_beta = th;
-    } else if (threadIdx.x == 64) {
-        __threadfence();  // this block's read of the step count is done
-        s_last = atomicAdd(arrive, 1) == (int)gridDim.x - 1;
-        if (l == 0 && E) {
-            double e = 0.0;
-            for (int w = 0; w < NW; ++w) e += red[2][w];
-            E[b] = e;
-        }
+    } else if (threadIdx.x == 64 && l == 0 && E) {
+        double e = 0.0;
+        for (int w = 0; w < NW; ++w) e += red[2][w];
+        E[b] = e;
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        *step = t;
-        *arrive = 0;
-    }
     // the new angles' tables: the rotation parameters on the last thread,
     // beside the phase-table entries of the others
     if (threadIdx.x == THREADS - 1) prep_coef(ws, sd, l, s_beta);
@@ -189,11 +181,22 @@ __global__ __launch_bounds__(THREADS) void k_reduce_adam(uint8_t* ws, const SubD
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_reduce_adam(uint8_t* ws, const SubDesc* subs, int B, int p, Partials part, double* theta,
-                              double* m, double* v, int32_t* step, int32_t* arrive, double lr, double b1, double b2,
-                              double eps, double* E, hipStream_t s)
+                              double* m, double* v, const int32_t* step, int32_t it, double lr, double b1,
+                              double b2, double eps, double* E, hipStream_t s)
 {
     hipLaunchKernelGGL(k_reduce_adam, dim3(B * p), dim3(THREADS), 0, s, ws, subs, B, p, part, theta, m, v, step,
-                       arrive, lr, b1, b2, eps, E);
+                       it, lr, b1, b2, eps, E);
+    return hipGetLastError();
+}
+
+__global__ void k_step_advance(int32_t* step, int32_t n)
+{
+    if (threadIdx.x == 0) *step += n;
+}
+
+hipError_t launch_step_advance(int32_t* step, int32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, step, n);
     return hipGetLastError();
 }
 
