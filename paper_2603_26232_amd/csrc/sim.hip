@@ -743,28 +743,29 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
         // folded in (the rotations are linear, so the factor of the one after
         // may be applied before it)
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
-        const float2 F = HAS_PRE ? cmul(pre.Ff, post.Ff) : post.Ff;
+        // (the first pass also folds in the amplitude 2^(-(n-1)/2) of |+>)
+        const float amp = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
+        const float2 F = HAS_PRE ? cmul(pre.Ff, post.Ff) : make_float2(amp * post.Ff.x, amp * post.Ff.y);
         for (int i = tid; i < lut_len; i += THREADS) lut[i] = cmul(L[i], F);
         if constexpr (HAS_PRE) load_cut_L<LE>(cr, tab, tid, m_pre);
         else load_cut_L<LS>(cr, tab, tid, 0u);
     }
     if constexpr (KIND == F_LAST) load_cut_L<LE>(cr, tab, tid, m_end);
     float2 v[REGS];
-    if constexpr (KIND == F_FIRST) {
-        const float a = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
-#pragma unroll
-        for (int r = 0; r < REGS; ++r) v[r] = make_float2(a, 0.f);
-    } else {
-        load_state<LS, CH == 3>(v, st, geo, tid);
-    }
+    if constexpr (KIND != F_FIRST) load_state<LS, CH == 3>(v, st, geo, tid);
     __syncthreads();  // phase table staged
     if constexpr (HAS_PRE) {
         seg_rot<CH, FULL, true, PREC>(v, lds, geo.c, pre.t, tid);
         if constexpr (!HAS_PH) scale_regs(v, pre.Ff);
     }
     if constexpr (HAS_PH) {
+        if constexpr (KIND == F_FIRST) {
 #pragma unroll
-        for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
+            for (int r = 0; r < REGS; ++r) v[r] = lut[cr[r]];  // |+> after the phase separator
+        } else {
+#pragma unroll
+            for (int r = 0; r < REGS; ++r) v[r] = cmul(v[r], lut[cr[r]]);
+        }
         // FIRST walks start -> end, MID walks back end -> start
         seg_rot<CH, FULL, KIND == F_FIRST, PREC>(v, lds, geo.c, post.t, tid);
     }
