@@ -26,6 +26,8 @@ constexpr int LUT_MAX = 2048;  // phase table entries per layer (sum of weights 
 // the top bit clear are stored, scaled by sqrt(2) to unit norm.
 constexpr int HALF_BITS = TILE_BITS - 1;  // qubits 0..10 in group 0; tile bit 11 = the complement
 constexpr int SMALL_MAX_N = 13;  // n <= 13: the reduced state (<= 4096 amplitudes) is one workgroup's tile
+// the tile passes address a stored state with 32-bit byte offsets
+static_assert((8ull << (QAOA_MAX_QUBITS - 1)) <= (1ull << 32), "a stored state must fit 32-bit byte offsets");
 constexpr int B_GROUP_MAX = 8;   // active qubits of a strided (high) group
 
 // Per-subgraph descriptor, resident in the workspace.
