@@ -34,10 +34,15 @@ _lib = None
 
 
 def lib():
+    """The loaded oracle library. PQ_ORACLE_LIB names a prebuilt copy to load
+    instead (the sanitizer build of the test-suite); else oracle.c is built
+    here if needed."""
     global _lib
     if _lib is None:
-        build()
-        _lib = ct.CDLL(_LIB)
+        path = os.environ.get("PQ_ORACLE_LIB")
+        if not path:
+            path = build()
+        _lib = ct.CDLL(path)
         _declare(_lib)
     return _lib
 

@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--train-T", type=int, default=200)
     ap.add_argument("--fit-steps", type=int, default=4000)
     ap.add_argument("--model", default=None, help="load a trained model (.npz) instead of training")
-    ap.add_argument("--eval", choices=["c3", "c5", "both"], default="both")
+    ap.add_argument("--eval", choices=["c3", "c5", "both", "none"], default="both")
     ap.add_argument("--T-max", type=int, default=200)
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)

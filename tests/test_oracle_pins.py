@@ -5,6 +5,7 @@ import itertools
 import json
 import math
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -337,6 +338,107 @@ def test_adam_update_matches_definition():
     oracle.adam_update(theta, g1, m, v, 1, lr=0.1)
     # first bias-corrected step is lr * sign(g) (up to eps)
     assert np.allclose(theta, [0.2, -0.3], atol=1e-7)
+
+
+ADAM_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adam_worked_example.json")
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.5])
+@pytest.mark.parametrize("maximise", [True, False])
+def test_adam_update_worked_example(eps, maximise):
+    # four steps of a sign-alternating gradient with b1 != b2, against the
+    # moments and bias-corrected estimates worked out by hand in exact
+    # rationals from Kingma and Ba (2015), Algorithm 1; a second parameter
+    # sees -g/2 (moments scaled by -1/2 and 1/4)
+    gold = json.load(open(ADAM_GOLDEN))
+    c = {k: float(Fraction(x)) for k, x in gold["constants"].items()}
+    fr = lambda key, t: float(Fraction(gold[key][t]))
+    sgn = 1.0 if maximise else -1.0
+    theta = np.array([0.25, -0.5])
+    expect = theta.copy()
+    m = np.zeros(2)
+    v = np.zeros(2)
+    for t in range(4):
+        gt = fr("grad", t)
+        oracle.adam_update(theta, np.array([gt, -gt / 2]), m, v, t + 1, lr=c["lr"], b1=c["b1"], b2=c["b2"], eps=eps,
+                           maximise=maximise)
+        assert m == pytest.approx([fr("m", t), -fr("m", t) / 2], abs=1e-15)
+        assert v == pytest.approx([fr("v", t), fr("v", t) / 4], abs=1e-15)
+        mh, vh = fr("mhat", t), fr("vhat", t)
+        expect += sgn * c["lr"] * np.array([mh / (math.sqrt(vh) + eps), (-mh / 2) / (math.sqrt(vh / 4) + eps)])
+        assert theta == pytest.approx(expect, abs=1e-14)
+    if eps == 0.0:
+        # the two parameters moved by opposite steps of equal size
+        assert theta[0] - 0.25 == pytest.approx(-(theta[1] + 0.5), abs=1e-15)
+
+
+def test_adam_solve_follows_adam_on_the_closed_form_gradient():
+    # K2 at p = 1: E = 1/2 + 1/2 sin(4 beta) sin(gamma) (pin 5), so
+    # dE/dgamma = 1/2 sin(4 beta) cos(gamma), dE/dbeta = 2 cos(4 beta) sin(gamma).
+    # The optimiser's own Adam loop must equal Adam (pinned above) driven by
+    # that closed-form gradient; with lr = 0.3 the trajectory overshoots, so
+    # both gradient components change sign along the way.
+    u, v = _edges([(0, 1)])
+    C = oracle.cut_table(2, u, v)
+    b1, b2, lr, T = 0.5, 0.75, 0.3, 6
+    gam, bet, hist = oracle.adam_solve(2, C, [1.2], [0.55], T=T, lr=lr, b1=b1, b2=b2, eps=0.0)
+    theta = np.array([1.2, 0.55])
+    m = np.zeros(2)
+    vv = np.zeros(2)
+    signs = []
+    closed = lambda g, b: 0.5 + 0.5 * math.sin(4 * b) * math.sin(g)
+    for t in range(T):
+        g, b = theta
+        assert hist[t] == pytest.approx(closed(g, b), abs=1e-13)
+        grad = np.array([0.5 * math.sin(4 * b) * math.cos(g), 2 * math.cos(4 * b) * math.sin(g)])
+        signs.append(np.sign(grad))
+        oracle.adam_update(theta, grad, m, vv, t + 1, lr=lr, b1=b1, b2=b2, eps=0.0)
+    assert gam[0] == pytest.approx(theta[0], abs=1e-12) and bet[0] == pytest.approx(theta[1], abs=1e-12)
+    assert hist[T] == pytest.approx(closed(*theta), abs=1e-13)
+    signs = np.array(signs)
+    assert np.all((signs > 0).any(0) & (signs < 0).any(0))
+
+
+def _ragged_batch():
+    sizes = [4, 6, 2, 5, 3, 7]
+    edges = []
+    for i, n in enumerate(sizes):
+        g = synth.erdos_renyi(n, 0.6, 40 + i)
+        edges.append((g.u, g.v, g.w))
+    edges[4] = (np.zeros(0, np.int32),) * 3  # an edgeless subgraph
+    assert len(edges[1][0]) > 0
+    return sizes, edges
+
+
+@pytest.mark.parametrize("canonical", [True, False])
+def test_eval_batch_equals_per_subgraph_functions(canonical):
+    sizes, edges = _ragged_batch()
+    p, k = 2, 3
+    gamma, beta = synth.uniform_angles(77, p, batch=len(sizes))
+    E, idx, prob = oracle.eval_batch(sizes, edges, gamma, beta, k=k, canonical=canonical)
+    for b, (n, (u, v, w)) in enumerate(zip(sizes, edges)):
+        C = oracle.cut_table(n, u, v, w)
+        psi = oracle.qaoa_state(n, C, gamma[b], beta[b])
+        assert E[b] == oracle.expectation(n, psi, C)
+        oi, op, ke = oracle.topk(n, psi, k, canonical=canonical)
+        assert np.array_equal(idx[b], oi) and np.array_equal(prob[b], op)
+
+
+def test_solve_batch_equals_per_subgraph_functions():
+    sizes, edges = _ragged_batch()
+    p, T, k = 2, 5, 3
+    g0, b0 = synth.uniform_angles(78, p, batch=len(sizes))
+    gf, bf, E, idx, prob = oracle.solve_batch(sizes, edges, g0, b0, T, k, lr=0.07, b1=0.8, b2=0.95)
+    for b, (n, (u, v, w)) in enumerate(zip(sizes, edges)):
+        C = oracle.cut_table(n, u, v, w)
+        g, be, hist = oracle.adam_solve(n, C, g0[b], b0[b], T, lr=0.07, b1=0.8, b2=0.95)
+        assert np.array_equal(gf[b], g) and np.array_equal(bf[b], be)
+        psi = oracle.qaoa_state(n, C, g, be)
+        assert E[b] == oracle.expectation(n, psi, C) == hist[T]
+        oi, op, ke = oracle.topk(n, psi, k)
+        assert np.array_equal(idx[b], oi) and np.array_equal(prob[b], op)
+    # the edgeless subgraph never moves (its gradient is exactly 0)
+    assert np.array_equal(gf[4], g0[4]) and np.array_equal(bf[4], b0[4]) and E[4] == 0.0
 
 
 # ---------------------------------------------------------------- Alg. 1
