@@ -1,29 +1,37 @@
 #!/usr/bin/env python3
 """Benchmark of the ParaQAOA hot path on one MI355X.
 
-Default workload (plain400): one step = one whole plain-method solve of the
-400-vertex graph: batch build with integer cut tables, 50 Adam steps of every
+Default workload (ragged2000): one step = one whole plain-method solve of a
+2000-vertex graph: batch build with integer cut tables, 50 Adam steps of every
 subgraph's angles on exact adjoint gradients, the final state and <C>, top-16
 extraction, the level-wise beam merge (W = 4096) and the integer CutVal of the
-winner. Erdos-Renyi G(400, 0.05), seed 0, unit weights, partitioned into 21
-chained subgraphs of 20 vertices (20 qubits, 2^20 complex64 amplitudes each),
-QAOA depth p = 3. Consecutive solves are pipelined: a solve's merge and CutVal
-run on a second stream while the next solve starts (--no-overlap runs them in
-line); the timed region still ends when every solve's merge has finished.
+winner. Erdos-Renyi G(2000, 0.01), seed 0, unit weights, partitioned into a
+chain of ragged subgraphs of 14..26 vertices (sizes from stream seed 1);
+edgeless subgraphs are not simulated (closed form); QAOA depth p = 3.
+Consecutive solves are pipelined: a solve's merge and CutVal run on a second
+stream while the next solve starts (--no-overlap runs them in line); the timed
+region still ends when every solve's merge has finished.
+
+The same line carries the learned-warm-start solve of the same graph: the
+angle predictor (committed weights, trained on plain-method runs of other
+seeds) gives every subgraph its starting angles on the device, each subgraph
+falls back to the plain method's cold start where that start has the larger
+<C>, then 10 Adam steps and the same finish. Both solve times (pipelined, and
+the latency of one solve run alone with its merge in line) and both merged cuts
+are reported.
 
 Other workloads (--workload):
-  ragged2000   the same solve on G(2000, 0.01), seed 0, a chain of ragged
-               subgraphs of 14..26 vertices (sizes from stream seed 1), edgeless
-               subgraphs skipped (closed form); reports the 2k-vertex solve time.
+  plain400     the same plain solve on G(400, 0.05), seed 0, 21 subgraphs of
+               20 vertices (equal partition, stride 19).
   precision26  one forward evaluation (all layers + <C>) of 32 random 3-regular
                graphs on 26 vertices, p = 4, angles U(0, pi); --mixer picks the
                mixer precision mode.
 
-value = amplitude updates per second: per forward evaluation every layer
-applies n RX gates and one diagonal phase to each amplitude, U = sum_b
-p (n_b + 1) 2^n_b over simulated subgraphs; an optimiser step is a forward
-evaluation plus the adjoint sweep over two states (3 U), and the final
-evaluation adds U.
+value = amplitude updates per second of the plain solves: per forward
+evaluation every layer applies n RX gates and one diagonal phase to each
+amplitude, U = sum_b p (n_b + 1) 2^n_b over simulated subgraphs; an optimiser
+step is a forward evaluation plus the adjoint sweep over two states (3 U),
+and the final evaluation adds U.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -87,8 +95,40 @@ def amp_updates(sizes, p):
     return sum(p * (int(n) + 1) * (1 << int(n)) for n in sizes)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu shows it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_solves(run, n, sync_each=False):
+    """Seconds per solve of `n` calls of run() (after a device sync); with
+    sync_each, the median of single solves each waited for (latency)."""
+    import torch
+    torch.cuda.synchronize()
+    if sync_each:
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2]
+    t0 = time.perf_counter()
+    for _ in range(n):
+        run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / n
+
+
 def workload_solve(args, name):
-    """plain400 / ragged2000: the plain-method solve as one step."""
+    """plain400 / ragged2000: the plain-method solve as one step; ragged2000
+    also times the learned-warm-start solve of the same graph."""
     import numpy as np
     from paper_2603_26232_amd import synth
     from paper_2603_26232_amd.partition import partition_equal, partition_chain
@@ -104,52 +144,115 @@ def workload_solve(args, name):
         g = synth.erdos_renyi(2000, 0.01, 0)
         part = partition_chain(2000, synth.ragged_sizes(1, 14, 26, 2000))
         skip = True
-        desc = "plain-method solve, G(2000,0.01) seed 0, ragged chain of 14..26-qubit subgraphs, edgeless " \
-               "skipped, p=3, 50 Adam steps, top-16, beam 4096, CutVal"
+        desc = "2k-vertex solve: G(2000,0.01) seed 0, ragged chain of 14..26-qubit subgraphs, edgeless " \
+               "skipped, p=3, top-16, beam 4096, CutVal; plain = cold start + 50 Adam steps, learned = " \
+               f"predicted start (cold-start fallback per subgraph) + {args.warm_iters} Adam steps"
     cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
     log(f"bench: graph {g}, {part.M} subgraphs of sizes {min(part.size)}..{max(part.size)}, p={cfg.p}, "
         f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
     S = Solver(g, part, cfg, skip_edgeless=skip)
     nE = np.array([len(e[0]) for e in S.sub_edges])
+    act = nE > 0
     sim = [int(n) for n, e in zip(part.size, nE) if not (skip and e == 0)]
     U = amp_updates(sim, cfg.p)
+    overlap = not args.no_overlap
+
+    LS = None
+    if name == "ragged2000" and not args.no_learned:
+        from paper_2603_26232_amd.learned import AnglePredictor, LearnedStart
+        model = AnglePredictor.from_file(args.predictor)
+        LS = LearnedStart(S, model)
+        log(f"bench: angle predictor {os.path.basename(args.predictor)} ({model.npar} parameters)")
 
     def step():
         S.rebuild()
-        S.run(graph=args.graph, overlap=not args.no_overlap)
+        S.run(graph=args.graph, overlap=overlap)
+
+    def learned_step(ov=overlap):
+        S.rebuild()
+        S.run_learned(LS, args.warm_iters, overlap=ov)
+
+    def plain_alone():
+        S.rebuild()
+        S.run(graph=args.graph, overlap=False)
+
+    def result():
+        r = S.result()
+        return {"cut": r.cut, "sum_E_with_edges": round(float(np.sum(r.energies[act])), 6)}
 
     def summary():
-        r = S.result()
-        return {"solve": {"cut": r.cut, "sum_E": float(np.sum(r.energies))}}
+        return {"solve": result()}
+
+    def extra(plain_s):
+        """After the timed plain solves: their result, the learned solves
+        timed the same way, and the latency of one solve of each kind."""
+        if LS is None:
+            return {}
+        out = {"plain": dict(result(), seconds=round(plain_s, 4), adam_steps=cfg.iters)}
+        log(f"bench: learned-warm-start solves ({args.warm_iters} Adam steps), {args.steps} timed")
+        learned_step()
+        learned_s = time_solves(learned_step, args.steps)
+        out["learned"] = dict(result(), seconds=round(learned_s, 4), adam_steps=args.warm_iters)
+        log(f"bench: latency of single solves (merge in line), {args.latency_solves} of each")
+        out["plain"]["latency_seconds"] = round(time_solves(plain_alone, args.latency_solves, True), 4)
+        out["learned"]["latency_seconds"] = round(time_solves(lambda: learned_step(False), args.latency_solves,
+                                                              True), 4)
+        out["learned_vs_plain"] = {"speedup": round(plain_s / learned_s, 3),
+                                   "latency_speedup": round(out["plain"]["latency_seconds"] /
+                                                            out["learned"]["latency_seconds"], 3),
+                                   "cut_ratio": round(out["learned"]["cut"] / out["plain"]["cut"], 4)}
+        log(f"bench: plain {plain_s:.3f} s/solve cut {out['plain']['cut']}; learned {learned_s:.3f} s/solve "
+            f"cut {out['learned']['cut']}")
+        return {"solve": out}
 
     def cpu_baseline():
         import oracle
         # bounded sample: every subgraph (plain400) or every 2nd simulated
         # subgraph of at most 22 qubits (ragged2000), T Adam steps with the
-        # final evaluation
+        # final evaluation; then a quarter of it on one thread
         idx = list(range(part.M)) if name == "plain400" else \
             [b for b in range(part.M) if not (skip and nE[b] == 0) and part.size[b] <= 22][::2]
         which = "all" if name == "plain400" else "every 2nd simulated one of at most 22 qubits"
         T = args.cpu_iters
-        sizes = [int(part.size[b]) for b in idx]
-        edges = [S.sub_edges[b] for b in idx]
-        g0, b0 = cold_start(cfg.p, len(idx))
-        log(f"bench: CPU baseline: FP64 oracle, {len(idx)} subgraphs x ({T} Adam steps + final evaluation)")
-        c0 = time.perf_counter()
-        oracle.solve_batch(sizes, edges, g0, b0, T, cfg.k, lr=cfg.lr)
-        c1 = time.perf_counter()
-        val = (3 * T + 1) * amp_updates(sizes, cfg.p) / (c1 - c0)
-        return {"value": val, "unit": "amp-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-                "seconds": round(c1 - c0, 2),
-                "sample": f"{len(idx)} subgraphs ({which}) of this workload, {T} Adam steps with adjoint "
-                          f"gradients + final evaluation and top-{cfg.k} (FP64)"}
 
-    config = {"workload": desc, "graph_replay": bool(args.graph), "merge_overlaps_next_solve": not args.no_overlap,
+        def timed(ids, T):
+            sizes = [int(part.size[b]) for b in ids]
+            edges = [S.sub_edges[b] for b in ids]
+            g0, b0 = cold_start(cfg.p, len(ids))
+            c0 = time.perf_counter()
+            oracle.solve_batch(sizes, edges, g0, b0, T, cfg.k, lr=cfg.lr)
+            c1 = time.perf_counter()
+            return (3 * T + 1) * amp_updates(sizes, cfg.p) / (c1 - c0), c1 - c0
+
+        threads = oracle.num_threads()
+        log(f"bench: CPU baseline: FP64 oracle, {len(idx)} subgraphs x ({T} Adam steps + final evaluation), "
+            f"{threads} threads")
+        val, sec = timed(idx, T)
+        one = idx[::4]
+        T1 = max(1, T // 3)
+        log(f"bench: CPU baseline: {len(one)} subgraphs x ({T1} Adam steps + final evaluation), 1 thread")
+        oracle.set_num_threads(1)
+        try:
+            val1, sec1 = timed(one, T1)
+        finally:
+            oracle.set_num_threads(threads)
+        return {"value": val, "unit": "amp-updates/s", "cores": threads, "kind": "oracle",
+                "seconds": round(sec, 2), "cpu_model": cpu_model(),
+                "sample": f"{len(idx)} subgraphs ({which}) of this workload, {T} Adam steps with adjoint "
+                          f"gradients + final evaluation and top-{cfg.k} (FP64)",
+                "one_thread": {"value": val1, "unit": "amp-updates/s", "cores": 1, "seconds": round(sec1, 2),
+                               "sample": f"every 4th subgraph of that sample ({len(one)}), {T1} Adam steps + "
+                                         f"final evaluation"}}
+
+    config = {"workload": desc, "graph_replay": bool(args.graph), "merge_overlaps_next_solve": overlap,
               "vertices": g.num_vertices, "edges": g.num_edges,
               "subgraphs": part.M, "simulated_subgraphs": len(sim),
               "qubits": [int(min(part.size)), int(max(part.size))],
               "p": cfg.p, "adam_steps": cfg.iters, "k": cfg.k, "beam": cfg.beam}
-    return dict(step=step, updates=(3 * cfg.iters + 1) * U, config=config, summary=summary,
+    if LS is not None:
+        config["learned_adam_steps"] = args.warm_iters
+        config["predictor"] = os.path.basename(args.predictor)
+    return dict(step=step, updates=(3 * cfg.iters + 1) * U, config=config, summary=summary, extra=extra,
                 cpu_baseline=cpu_baseline, close=S.close, dtype="fp32")
 
 
@@ -186,7 +289,7 @@ def workload_precision(args):
         oracle.eval_batch(sizes, sub, gamma[:2], beta[:2])
         c1 = time.perf_counter()
         return {"value": amp_updates(sizes, 4) / (c1 - c0), "unit": "amp-updates/s",
-                "cores": oracle.num_threads(), "kind": "oracle", "seconds": round(c1 - c0, 2),
+                "cores": oracle.num_threads(), "kind": "oracle", "seconds": round(c1 - c0, 2), "cpu_model": cpu_model(),
                 "sample": "2 of the 32 subgraphs (26 qubits, p = 4), one FP64 forward evaluation with <C>"}
 
     dtype = {"valu": "fp32", "mfma_f32": "fp32", "mfma_bf16x3": "bf16x3 (mixer block)",
@@ -202,12 +305,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["plain400", "ragged2000", "precision26"], default="plain400")
+    ap.add_argument("--workload", choices=["ragged2000", "plain400", "precision26"], default="ragged2000")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run each solve's merge on the main stream instead of overlapping it with the next solve")
     ap.add_argument("--mixer", choices=["valu", "mfma_f32", "mfma_bf16x3", "mfma_bf16x4"], default="valu",
                     help="mixer precision mode (precision26 only)")
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
+    ap.add_argument("--no-learned", action="store_true", help="ragged2000: skip the learned-warm-start solves")
+    ap.add_argument("--warm-iters", type=int, default=10, help="Adam steps of a learned-warm-start solve")
+    ap.add_argument("--predictor", default=None, help="trained angle predictor (.npz); default: the package's")
+    ap.add_argument("--latency-solves", type=int, default=3, help="single solves timed alone, per kind")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the Adam step from a captured HIP graph")
     ap.add_argument("--tuning", default="default",
@@ -224,6 +331,9 @@ def main():
 
     import torch
     from paper_2603_26232_amd import _abi
+    if args.predictor is None:
+        from paper_2603_26232_amd.learned import DEFAULT_MODEL
+        args.predictor = DEFAULT_MODEL
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
@@ -332,13 +442,15 @@ def main():
     out["kernels_warmup_step"] = {k: {"launches": v["launches"], "avg_us": round(v["avg_us"], 2),
                                       "algo_GBs": round(v["algo_bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
                                       if v["total_ms"] else 0} for k, v in kern.items()}
-    if args.workload == "ragged2000":
-        out["solve_seconds"] = ms_step / 1e3
+    if "extra" in W:
+        out.update(W["extra"](ms_step / 1e3))
     W["close"]()
     if not args.no_cpu_baseline:
         cb = W["cpu_baseline"]()
         out["cpu_baseline"] = cb
         log(f"bench: CPU baseline {cb['value']:.4e} amp-updates/s in {cb['seconds']} s on {cb['cores']} threads")
+        if "one_thread" in cb:
+            log(f"bench: CPU baseline {cb['one_thread']['value']:.4e} amp-updates/s on 1 thread")
     print(json.dumps(out), flush=True)
 
 

@@ -282,6 +282,27 @@ qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_t hidden, i
                                 const float* d_target, void* d_scratch, size_t scratch_bytes, double* d_grad,
                                 double* d_loss, qaoa_stream_t stream);
 
+/* Learned warm start, step 1: the predictor's outputs as starting angles.
+ * y[b][o] holds the standardised output o of subgraph b (o < p: gamma_{o+1},
+ * o >= p: beta_{o-p+1}); the angle is y * sd[o] + mu[o], computed in FP32
+ * (product, then sum, each rounded) and widened to FP64.
+ *   d_y        device float [B][2p] (qaoa_mlp_forward's output, out = 2p)
+ *   d_mu, d_sd device float [2p], the target standardisation of training
+ *   d_theta    device double [2*B*p] receiving [gamma (B*p) | beta (B*p)] in
+ *              the layout of qaoa_optimize
+ * QAOA_ERR_OUT_OF_RANGE for p outside 1..32. */
+qaoa_status_t qaoa_warm_angles(int32_t B, int32_t p, const float* d_y, const float* d_mu, const float* d_sd,
+                               double* d_theta, qaoa_stream_t stream);
+
+/* Learned warm start, step 2: the plain method's start stays the fallback.
+ * For every subgraph b, if d_E_alt[b] > d_E[b] (the alternative start has the
+ * larger <C>, Sec. 2.2's objective), its angles replace row b of d_theta
+ * (gamma and beta) and d_E[b] becomes d_E_alt[b]; otherwise row b is kept.
+ *   d_E_alt, d_E           device double [B]
+ *   d_theta_alt, d_theta   device double [2*B*p], layout of qaoa_optimize */
+qaoa_status_t qaoa_keep_better(int32_t B, int32_t p, const double* d_E_alt, const double* d_theta_alt, double* d_E,
+                               double* d_theta, qaoa_stream_t stream);
+
 /* Where subgraph b's state lives: the byte offset, inside the workspace, of
  * its stored amplitudes. The ansatz state is invariant under flipping every
  * bit (H_C, H_M and |+>^n all commute with X on every qubit, Sec. 2.2), so
@@ -322,7 +343,7 @@ const char* qaoa_last_error(void);
  * passes by direction, kind and qubit group, "fwd_{first,single,mid,last}_gG"
  * and "bwd_{fused,single,mid,last,single_nopsi,mid_nopsi}_gG" (G = 0..3), and
  * "small", "cut_tables", "angle_prep", "reduce", "topk", "maxcut", "adam",
- * "merge", "mlp_forward", "mlp_backward". Not for use while another thread
+ * "merge", "mlp_forward", "mlp_backward", "warm_angles", "keep_better". Not for use while another thread
  * launches. */
 qaoa_status_t qaoa_profile_enable(int32_t on);
 /* Restrict the timing to one kernel name (NULL or "" = all). Each timed launch

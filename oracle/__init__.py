@@ -57,6 +57,8 @@ _c128p = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
 
 def _declare(L):
     L.or_num_threads.restype = ct.c_int
+    L.or_set_num_threads.restype = None
+    L.or_set_num_threads.argtypes = [ct.c_int]
     L.or_cutval.restype = ct.c_int64
     L.or_cutval.argtypes = [ct.c_int64, _i32p, _i32p, ct.c_void_p, _u8p]
     L.or_cutval_packed.restype = None
@@ -120,6 +122,11 @@ def _wptr(w):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP loops from now on (1 = a single core)."""
+    lib().or_set_num_threads(int(n))
 
 
 # --- Sec. 2.1 -------------------------------------------------------------

@@ -45,6 +45,16 @@ int or_num_threads(void)
 #endif
 }
 
+/* Number of threads the later parallel loops use (timing on one core). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. 2.1: CutVal(x) = sum of w_uv over edges whose endpoints are on       */
 /* different sides of the bipartition x (x[v] in {0,1}).                     */

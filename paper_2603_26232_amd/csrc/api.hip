@@ -1093,3 +1093,29 @@ extern "C" qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_
     HIP_TRY(launch_mlp_backward(batch, d, d_params, d_x, d_y, d_act, d_target, (float*)d_scratch, d_grad, d_loss, st));
     return ok();
 }
+
+extern "C" qaoa_status_t qaoa_warm_angles(int32_t B, int32_t p, const float* d_y, const float* d_mu,
+                                          const float* d_sd, double* d_theta, qaoa_stream_t stream)
+{
+    if (B < 1) return fail(QAOA_ERR_INVALID_ARG, "B = %d", B);
+    if (p < 1 || p > MAX_P) return fail(QAOA_ERR_OUT_OF_RANGE, "p = %d outside 1..%d", p, MAX_P);
+    if ((int64_t)2 * B * p > INT32_MAX) return fail(QAOA_ERR_OUT_OF_RANGE, "2 B p too large");
+    if (!d_y || !d_mu || !d_sd || !d_theta) return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("warm_angles", st, (4.0 + 8.0) * 2.0 * B * p);
+    HIP_TRY(launch_warm_angles(B, p, d_y, d_mu, d_sd, d_theta, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_keep_better(int32_t B, int32_t p, const double* d_E_alt, const double* d_theta_alt,
+                                          double* d_E, double* d_theta, qaoa_stream_t stream)
+{
+    if (B < 1) return fail(QAOA_ERR_INVALID_ARG, "B = %d", B);
+    if (p < 1 || p > MAX_P) return fail(QAOA_ERR_OUT_OF_RANGE, "p = %d outside 1..%d", p, MAX_P);
+    if ((int64_t)2 * B * p > INT32_MAX) return fail(QAOA_ERR_OUT_OF_RANGE, "2 B p too large");
+    if (!d_E_alt || !d_theta_alt || !d_E || !d_theta) return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps("keep_better", st, 8.0 * 3.0 * B);
+    HIP_TRY(launch_keep_better(B, p, d_E_alt, d_theta_alt, d_E, d_theta, st));
+    return ok();
+}

@@ -142,6 +142,10 @@ inline size_t mlp_scratch_bytes(int B, const MlpDims& d)
     return sizeof(float) * ((size_t)B * (2 * d.H + d.out) + 2) + sizeof(double) * (size_t)B + 8;
 }
 hipError_t launch_mlp_forward(int B, MlpDims d, const double* P, const float* X, float* Y, float* act, hipStream_t s);
+hipError_t launch_warm_angles(int B, int p, const float* Y, const float* mu, const float* sd, double* theta,
+                              hipStream_t s);
+hipError_t launch_keep_better(int B, int p, const double* E_alt, const double* theta_alt, double* E, double* theta,
+                              hipStream_t s);
 hipError_t launch_mlp_backward(int B, MlpDims d, const double* P, const float* X, const float* Y, const float* act,
                                const float* T, float* scratch, double* G, double* loss, hipStream_t s);
 
@@ -186,12 +190,14 @@ __device__ inline double block_sum(double x, double* red)
 
 // Adam (Kingma and Ba 2015) update of one parameter in FP64 with the bias
 // corrections c1 = 1 - b1^t, c2 = 1 - b2^t; sign +1 ascends. The standalone
-// step and the fused optimiser kernel share it; every operation is an
-// explicitly rounded one (no contraction into FMAs, which the compiler could
-// choose differently in the two kernels), so both give the same bits.
+// step and the fused optimiser kernel share it; floating-point contraction is
+// off in its body, so every product and sum is rounded on its own (no FMAs,
+// which the compiler could choose differently in the two kernels) and both
+// give the same bits.
 __device__ __noinline__ inline void adam_update(double& th, double& m, double& v, double g, double c1, double c2, double lr,
                                    double b1, double b2, double eps, double sign)
 {
+#pragma clang fp contract(off)
     const double mi = __dadd_rn(__dmul_rn(b1, m), __dmul_rn(__dsub_rn(1.0, b1), g));
     const double vi = __dadd_rn(__dmul_rn(b2, v), __dmul_rn(__dmul_rn(__dsub_rn(1.0, b2), g), g));
     m = mi;

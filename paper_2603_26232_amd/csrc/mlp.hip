@@ -149,6 +149,53 @@ __global__ void k_mlp_loss(int B, int out, const double* sq, double* loss)
     }
 }
 
+// Warm-start angles from the predictor's standardised outputs: output o of
+// subgraph b becomes y * sd[o] + mu[o] (FP32, rounded as written), then FP64;
+// outputs 0..p-1 are gamma_1..p, outputs p..2p-1 are beta_1..p, and theta is
+// laid out [gamma (B p) | beta (B p)], row b = subgraph b.
+__global__ void k_warm_angles(int B, int p, const float* Y, const float* mu, const float* sd, double* theta)
+{
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * B * p) return;
+    const int b = i / (2 * p), o = i % (2 * p);
+    const float a = Y[i] * sd[o] + mu[o];  // two roundings, never one fused multiply-add
+    const size_t dst = o < p ? (size_t)b * p + o : (size_t)B * p + (size_t)b * p + (o - p);
+    theta[dst] = (double)a;
+}
+
+// Per subgraph, keep the start with the larger <C>: if E_alt[b] > E[b], row b
+// of theta (its gamma and beta) and E[b] take the alternative's values. One
+// thread per subgraph, so the comparison and the copy see the same E[b].
+__global__ void k_keep_better(int B, int p, const double* E_alt, const double* theta_alt, double* E, double* theta)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double ea = E_alt[b];
+    if (!(ea > E[b])) return;
+    for (int l = 0; l < p; ++l) {
+        const size_t g = (size_t)b * p + l, t = (size_t)B * p + g;
+        theta[g] = theta_alt[g];
+        theta[t] = theta_alt[t];
+    }
+    E[b] = ea;
+}
+
+hipError_t launch_warm_angles(int B, int p, const float* Y, const float* mu, const float* sd, double* theta,
+                              hipStream_t s)
+{
+    const int n = 2 * B * p;
+    hipLaunchKernelGGL(k_warm_angles, dim3((n + 255) / 256), dim3(256), 0, s, B, p, Y, mu, sd, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_keep_better(int B, int p, const double* E_alt, const double* theta_alt, double* E, double* theta,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_keep_better, dim3((B + 255) / 256), dim3(256), 0, s, B, p, E_alt, theta_alt, E, theta);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_forward(int B, MlpDims d, const double* P, const float* X, float* Y, float* act, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mlp_fwd, dim3(B), dim3(MLP_MAX_H), 0, s, B, d, P, X, Y, act);

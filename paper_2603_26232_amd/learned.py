@@ -17,6 +17,7 @@ ansatz's exact symmetries for integer cut values: beta_l -> beta_l + pi/2
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import torch
@@ -131,3 +132,78 @@ class AnglePredictor:
     def load(self, st: dict):
         self.params = torch.as_tensor(st["params"], device=self.device)
         self.x_mu, self.x_sd, self.y_mu, self.y_sd = st["x_mu"], st["x_sd"], st["y_mu"], st["y_sd"]
+
+    @classmethod
+    def from_file(cls, path: str, device="cuda") -> "AnglePredictor":
+        """A trained predictor saved from `state()` with numpy.savez (plain
+        arrays only; loaded without pickle)."""
+        with np.load(path, allow_pickle=False) as z:
+            st = {k: z[k] for k in z.files}
+        p = int(st["p"])
+        n_in = int(st["x_mu"].shape[0])
+        m = cls(p, device=device, in_dim=n_in, hidden=_hidden_width(n_in, 2 * p, int(st["params"].shape[0])))
+        m.load(st)
+        return m
+
+
+def _hidden_width(n_in: int, out: int, count: int) -> int:
+    """Hidden width H of an n_in -> H -> H -> out network with `count`
+    parameters: H (n_in + 1) + H (H + 1) + out (H + 1) = count."""
+    b = n_in + 2 + out
+    H = int(round((-b + math.sqrt(b * b + 4 * (count - out))) / 2))
+    if H * (n_in + 1) + H * (H + 1) + out * (H + 1) != count:
+        raise ValueError(f"{count} parameters do not form an {n_in} -> H -> H -> {out} network")
+    return H
+
+
+DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "angle_mlp_p3.npz")
+
+
+class LearnedStart:
+    """Learned warm start of one Solver's batch, on the device.
+
+    Built once per graph (input preparation, like the partition): the
+    standardised feature rows of every subgraph, the predictor's parameters
+    and target standardisation, and buffers for the two candidate starts.
+    `start()` only enqueues work: the predictor's forward pass, its outputs
+    turned into angles, <C> at the predicted and at the cold-start angles,
+    and per subgraph the start with the larger <C> (the plain method's
+    start remains the fallback)."""
+
+    def __init__(self, solver, model: AnglePredictor):
+        from .solve import cold_start
+        S = solver
+        assert model.p == S.cfg.p, f"predictor depth {model.p} != solve depth {S.cfg.p}"
+        self.S, self.model = S, model
+        dev = S.device
+        F = np.stack([features(int(S.part.size[b]), S.sub_edges[b][0], S.sub_edges[b][1]) for b in range(S.B)])
+        self.X = torch.as_tensor(((F - model.x_mu) / model.x_sd).astype(np.float32), device=dev)
+        self.mu = torch.as_tensor(np.asarray(model.y_mu, np.float32), device=dev)
+        self.sd = torch.as_tensor(np.asarray(model.y_sd, np.float32), device=dev)
+        self.Y = torch.empty((S.B, model.out), dtype=torch.float32, device=dev)
+        self.act = torch.empty((S.B, 2 * model.hidden), dtype=torch.float32, device=dev)
+        g0, b0 = cold_start(S.cfg.p, S.B)
+        self.theta_cold = torch.as_tensor(np.concatenate([g0.reshape(-1), b0.reshape(-1)]), device=dev)
+        self.theta_alt = torch.empty_like(self.theta_cold)
+        self.E_alt = torch.empty(S.B, dtype=torch.float64, device=dev)
+
+    def start(self, stream=None):
+        S, m = self.S, self.model
+        p, B = S.cfg.p, S.B
+        P = B * p
+        st = _stream(stream)
+        h = S.batch.handle
+        self.theta_alt.copy_(self.theta_cold)
+        ta = _ptr(self.theta_alt)
+        _abi.qaoa_apply_layers(h, p, ta, ta + 8 * P, st)
+        _abi.qaoa_expectation(h, _ptr(self.E_alt), st)
+        _abi.qaoa_mlp_forward(B, m.in_dim, m.hidden, m.out, _ptr(m.params), _ptr(self.X), _ptr(self.Y),
+                              _ptr(self.act), st)
+        th = _ptr(S.theta)
+        _abi.qaoa_warm_angles(B, p, _ptr(self.Y), _ptr(self.mu), _ptr(self.sd), th, st)
+        _abi.qaoa_apply_layers(h, p, th, th + 8 * P, st)
+        _abi.qaoa_expectation(h, _ptr(S.E), st)
+        _abi.qaoa_keep_better(B, p, _ptr(self.E_alt), ta, _ptr(S.E), th, st)
+        S.m.zero_()
+        S.v.zero_()
+        S.step.zero_()

@@ -221,6 +221,16 @@ class Solver:
             self.optimise(n, stream)
         self.finish(stream, overlap=overlap)
 
+    def run_learned(self, start, iters: int, stream=None, overlap=False):
+        """A learned-warm-start solve: `start` (a learned.LearnedStart of this
+        solver) enqueues the predicted angles, with each subgraph falling back
+        to the cold start where that start's <C> is larger; then `iters` Adam
+        steps and the same finish as the plain method (device only)."""
+        start.start(stream)
+        if iters > 0:
+            self.optimise(iters, stream)
+        self.finish(stream, overlap=overlap)
+
     def result(self) -> SolveResult:
         """The last finished solve's outputs (waits for the device)."""
         torch.cuda.synchronize()

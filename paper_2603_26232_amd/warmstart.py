@@ -26,17 +26,22 @@ import numpy as np
 import torch
 
 from . import synth
-from .learned import AnglePredictor, canonical_angles, features
+from .learned import AnglePredictor, LearnedStart, canonical_angles, features
 from .partition import partition_chain, partition_equal
 from .solve import Solver, SolveConfig, cold_start
 from .batch import _ptr, _stream
 from . import _abi
 
 
-def run_with_history(S: Solver, gamma0, beta0, iters: int):
-    """Adam steps from the given angles; returns E at the start of every step
-    and after the last ([iters + 1, B] numpy) and leaves the angles in S."""
-    S.set_angles(gamma0, beta0)
+def run_with_history(S: Solver, gamma0, beta0, iters: int, start=None):
+    """Adam steps from the given angles (or from a learned.LearnedStart's
+    start, with its per-subgraph cold-start fallback); returns E at the start
+    of every step and after the last ([iters + 1, B] numpy) and leaves the
+    angles in S."""
+    if start is not None:
+        start.start()
+    else:
+        S.set_angles(gamma0, beta0)
     hist = torch.zeros((iters + 1, S.B), dtype=torch.float64, device=S.device)
     cfg = S.cfg
     P = S.B * cfg.p
@@ -118,15 +123,14 @@ def compare(model: AnglePredictor, g, part, p=3, T_max=200, plain_iters=50, warm
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     r_plain = S.result()
-    # warm start
-    F = np.stack([features(int(part.size[b]), S.sub_edges[b][0], S.sub_edges[b][1]) for b in range(S.B)])
-    gw, bw = model.predict(F)
-    gw[~act] = g0[~act]
-    bw[~act] = b0[~act]
-    hist_warm = run_with_history(S, gw, bw, T_max)
+    # warm start: predicted angles on the device, each subgraph falling back
+    # to the cold start where that start's <C> is larger
+    LS = LearnedStart(S, model)
+    hist_warm = run_with_history(S, None, None, T_max, start=LS)
     it_warm = iterations_to_converge(hist_warm, E_star, nE)
     out = {"subgraphs": int(S.B), "with_edges": int(act.sum()), "T_max": T_max,
            "plain_iters": plain_iters, "plain_cut": r_plain.cut, "plain_solve_s": t_plain,
+           "plain_sum_E": float(r_plain.energies[act].sum()),
            "reference_run_s": t_ref,
            "iters_to_converge_cold": {"mean": float(it_cold[act].mean()), "median": float(np.median(it_cold[act]))},
            "iters_to_converge_warm": {"mean": float(it_warm[act].mean()), "median": float(np.median(it_warm[act]))},
@@ -135,13 +139,14 @@ def compare(model: AnglePredictor, g, part, p=3, T_max=200, plain_iters=50, warm
     for wi in warm_iters:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        S.run(gamma0=gw, beta0=bw, iters=wi)
+        S.run_learned(LS, wi)
         torch.cuda.synchronize()
         t_w = time.perf_counter() - t0
         r = S.result()
-        out["warm"].append({"iters": wi, "cut": r.cut, "solve_s": t_w, "cut_ratio_vs_plain": r.cut / r_plain.cut})
+        out["warm"].append({"iters": wi, "cut": r.cut, "solve_s": t_w, "cut_ratio_vs_plain": r.cut / r_plain.cut,
+                            "sum_E": float(r.energies[act].sum())})
         log(f"warmstart: warm start + {wi} steps: cut {r.cut} (plain {r_plain.cut} after {plain_iters}), "
-            f"{t_w:.3f} s vs {t_plain:.3f} s")
+            f"sum E {out['warm'][-1]['sum_E']:.3f} (plain {out['plain_sum_E']:.3f}), {t_w:.3f} s vs {t_plain:.3f} s")
     S.close()
     return out
 
@@ -162,8 +167,7 @@ def main():
     model = AnglePredictor(p, seed=0)
     result = {}
     if args.model:
-        st = dict(np.load(args.model))
-        model.load(st)
+        model = AnglePredictor.from_file(args.model)
     else:
         X, Y = collect(range(*args.train_seeds), T=args.train_T, log=log)
         log(f"warmstart: training set {X.shape[0]} subgraphs")

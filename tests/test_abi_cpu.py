@@ -111,6 +111,28 @@ def test_adam_arguments_are_checked_on_the_host():
         assert ei.value.status == status, args
 
 
+def test_warm_start_arguments_are_checked_on_the_host():
+    # fake non-NULL device pointers: every case fails its checks before any launch
+    for fn in (_abi.qaoa_warm_angles, _abi.qaoa_keep_better):
+        for (B, p, ptrs), status in [((0, 3, (8, 8, 8, 8)), 1), ((4, 0, (8, 8, 8, 8)), 2),
+                                     ((4, 33, (8, 8, 8, 8)), 2), ((4, 3, (0, 8, 8, 8)), 1),
+                                     ((4, 3, (8, 8, 8, 0)), 1)]:
+            with pytest.raises(_abi.QaoaError) as ei:
+                fn(B, p, *ptrs, 0)
+            assert ei.value.status == status, (fn.__name__, B, p, ptrs)
+
+
+def test_predictor_file_shape():
+    """The committed predictor holds plain arrays of an 18 -> 128 -> 128 -> 6
+    network (loaded without pickle)."""
+    from paper_2603_26232_amd.learned import DEFAULT_MODEL, N_FEATURES, _hidden_width
+    with np.load(DEFAULT_MODEL, allow_pickle=False) as z:
+        assert int(z["p"]) == 3
+        assert z["x_mu"].shape == (N_FEATURES,) and z["y_sd"].shape == (6,)
+        assert _hidden_width(N_FEATURES, 6, z["params"].shape[0]) == 128
+        assert np.all(np.isfinite(z["params"])) and np.all(z["y_sd"] > 0)
+
+
 # ---------------------------------------------------------------- host prep
 @pytest.mark.parametrize("nV,N", [(400, 20), (401, 20), (57, 5), (20, 20), (1000, 26)])
 def test_partition_matches_oracle(nV, N):

@@ -71,3 +71,35 @@ def test_adam_step_matches_oracle():
     torch.cuda.synchronize()
     assert int(step.cpu()[0]) == 5
     assert np.max(np.abs(dth.cpu().numpy() - theta)) <= 1e-12
+
+
+@pytest.mark.parametrize("B,p", [(1, 1), (104, 3), (777, 4)])
+def test_warm_angles_and_fallback(B, p):
+    """qaoa_warm_angles maps the predictor's standardised outputs to the
+    [gamma | beta] angle layout with y * sd + mu rounded in FP32 (bit-exact vs
+    numpy's float32 arithmetic); qaoa_keep_better takes, per subgraph, the
+    alternative's angles and <C> exactly where its <C> is strictly larger."""
+    rng = np.random.default_rng(B * 31 + p)
+    Y = rng.normal(size=(B, 2 * p)).astype(np.float32)
+    mu = rng.normal(size=2 * p).astype(np.float32)
+    sd = rng.uniform(0.1, 2.0, 2 * p).astype(np.float32)
+    dY, dmu, dsd = (torch.as_tensor(a, device="cuda") for a in (Y, mu, sd))
+    th = torch.full((2 * B * p,), np.nan, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    _abi.qaoa_warm_angles(B, p, _ptr(dY), _ptr(dmu), _ptr(dsd), _ptr(th), s)
+    A = (Y * sd + mu).astype(np.float64)  # numpy float32: product, then sum, each rounded
+    ref = np.concatenate([A[:, :p].reshape(-1), A[:, p:].reshape(-1)])
+    torch.cuda.synchronize()
+    assert np.array_equal(th.cpu().numpy(), ref)
+    # fallback: ties keep the current start
+    E = rng.integers(0, 4, B).astype(np.float64)
+    E_alt = rng.integers(0, 4, B).astype(np.float64)
+    th_alt = rng.normal(size=2 * B * p)
+    dE, dEa, dta = (torch.as_tensor(a.copy(), device="cuda") for a in (E, E_alt, th_alt))
+    _abi.qaoa_keep_better(B, p, _ptr(dEa), _ptr(dta), _ptr(dE), _ptr(th), s)
+    torch.cuda.synchronize()
+    take = E_alt > E
+    exp_th = ref.copy().reshape(2, B, p)
+    exp_th[:, take, :] = th_alt.reshape(2, B, p)[:, take, :]
+    assert np.array_equal(th.cpu().numpy(), exp_th.reshape(-1))
+    assert np.array_equal(dE.cpu().numpy(), np.where(take, E_alt, E))
