@@ -74,7 +74,7 @@ typedef void* qaoa_stream_t;
  * stored (qaoa_state_offset reports QAOA_ERR_STATE for them). */
 #define QAOA_FLAG_SKIP_EDGELESS 0x4u
 /* Precision modes of the mixer (Sec. 2.2: U_M(beta) = prod_j e^{-i beta X_j}).
- * For subgraphs with more than 12 qubits, the rotation of five of the qubits
+ * For subgraphs with more than 13 qubits, the rotation of five of the qubits
  * in the first qubit group (local qubits 0..3 and 9) runs as one dense
  * 32 x 32 complex block on the matrix cores instead of the vector units:
  *   MFMA_F32    FP32 matrix products (32x32x2);
@@ -86,7 +86,7 @@ typedef void* qaoa_stream_t;
  * Accumulation is FP32; all other steps are unchanged (FP32 amplitudes). At
  * most one mode may be set (QAOA_ERR_INVALID_ARG otherwise); none can be
  * combined with QAOA_FLAG_GRADIENT (QAOA_ERR_NOT_SUPPORTED). Subgraphs of at
- * most 12 qubits keep the vector path. */
+ * most 13 qubits keep the vector path. */
 #define QAOA_FLAG_MIXER_MFMA_F32 0x8u
 #define QAOA_FLAG_MIXER_MFMA_BF16X3 0x10u
 #define QAOA_FLAG_MIXER_MFMA_BF16X4 0x20u

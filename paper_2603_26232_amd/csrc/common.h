@@ -33,9 +33,9 @@ constexpr int B_GROUP_MAX = 8;   // active qubits of a strided (high) group
 // Per-subgraph descriptor, resident in the workspace.
 struct SubDesc {
     int32_t n;        // qubits
-    int32_t ngroups;  // 1 for n <= 12, else 1 + ceil((n-12)/8)
+    int32_t ngroups;  // 1 for n <= 13 (whole-state kernel), else 1 + ceil((n-12)/8)
     int32_t gstart[MAX_GROUPS];  // first qubit of group g (group 0 starts at 0)
-    int32_t gsize[MAX_GROUPS];   // qubits in group g (group 0 has min(n, 12))
+    int32_t gsize[MAX_GROUPS];   // qubits in group g (group 0: n when n <= 13, else 12)
     int32_t lut_len;  // sum of weights + 1 (phase table length per layer)
     int32_t ntiles;   // max(1, 2^(n-12))
     int32_t tile_base;  // first global tile index

@@ -954,7 +954,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
 }
 
 // ---------------------------------------------------------------------------
-// Subgraphs with n <= 12: one workgroup runs the whole circuit (and, with
+// Subgraphs with n <= 13: one workgroup runs the whole circuit (and, with
 // grad, the whole adjoint sweep) in LDS, one qubit at a time, with the
 // plain (cos, sin) form of each rotation.
 // ---------------------------------------------------------------------------
