@@ -303,6 +303,24 @@ qaoa_status_t qaoa_warm_angles(int32_t B, int32_t p, const float* d_y, const flo
 qaoa_status_t qaoa_keep_better(int32_t B, int32_t p, const double* d_E_alt, const double* d_theta_alt, double* d_E,
                                double* d_theta, qaoa_stream_t stream);
 
+/* qaoa_mlp_backward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training loops, harnesses that forbid
+ * allocation): the same kernels and results, with the scratch taken from a
+ * buffer the library holds in device memory (8 MiB per device, kept until
+ * the process ends) instead of a caller's d_scratch. The call allocates
+ * nothing: no device, host or pinned memory and no events.
+ *   Arguments as qaoa_mlp_backward, without d_scratch / scratch_bytes.
+ *   QAOA_ERR_OUT_OF_RANGE if qaoa_mlp_scratch_bytes(batch, in_dim, hidden,
+ *   out_dim) exceeds 8 MiB (e.g. batch > 8000 at in 18, hidden 128, out 6).
+ * Every call on a device shares that device's buffer (each call overwrites
+ * the part it uses before reading it; nothing needs to start at zero), so
+ * calls that overlap on one device race: issue them on one stream, or order
+ * them. The first call on a device looks up the buffer's address there. */
+qaoa_status_t qaoa_mlp_backward_noalloc(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                        const double* d_params, const float* d_x, const float* d_y,
+                                        const float* d_act, const float* d_target, double* d_grad, double* d_loss,
+                                        qaoa_stream_t stream);
+
 /* Where subgraph b's state lives: the byte offset, inside the workspace, of
  * its stored amplitudes. The ansatz state is invariant under flipping every
  * bit (H_C, H_M and |+>^n all commute with X on every qubit, Sec. 2.2), so

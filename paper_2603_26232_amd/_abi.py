@@ -76,6 +76,7 @@ def lib() -> ct.CDLL:
             "qaoa_mlp_scratch_bytes": [_i32, _i32, _i32, _i32, _vp],
             "qaoa_mlp_forward": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
             "qaoa_mlp_backward": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, ct.c_size_t, _vp, _vp, _vp],
+            "qaoa_mlp_backward_noalloc": [_i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
             "qaoa_warm_angles": [_i32, _i32, _vp, _vp, _vp, _vp, _vp],
             "qaoa_keep_better": [_i32, _i32, _vp, _vp, _vp, _vp, _vp],
             "qaoa_state_offset": [_vp, _i32, _vp],
@@ -236,6 +237,12 @@ def qaoa_warm_angles(B: int, p: int, d_y: int, d_mu: int, d_sd: int, d_theta: in
 
 def qaoa_keep_better(B: int, p: int, d_E_alt: int, d_theta_alt: int, d_E: int, d_theta: int, stream: int) -> None:
     _call("qaoa_keep_better", B, p, _vp(d_E_alt), _vp(d_theta_alt), _vp(d_E), _vp(d_theta), _vp(stream))
+
+
+def qaoa_mlp_backward_noalloc(batch, in_dim, hidden, out_dim, d_params, d_x, d_y, d_act, d_target, d_grad,
+                              d_loss, stream) -> None:
+    _call("qaoa_mlp_backward_noalloc", batch, in_dim, hidden, out_dim, _vp(d_params), _vp(d_x), _vp(d_y),
+          _vp(d_act), _vp(d_target), _vp(d_grad), _vp(d_loss), _vp(stream))
 
 
 def qaoa_state_offset(h: int, b: int) -> int:

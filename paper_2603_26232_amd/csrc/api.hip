@@ -1094,6 +1094,28 @@ extern "C" qaoa_status_t qaoa_mlp_backward(int32_t batch, int32_t in_dim, int32_
     return ok();
 }
 
+extern "C" qaoa_status_t qaoa_mlp_backward_noalloc(int32_t batch, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                                                   const double* d_params, const float* d_x, const float* d_y,
+                                                   const float* d_act, const float* d_target, double* d_grad,
+                                                   double* d_loss, qaoa_stream_t stream)
+{
+    qaoa_status_t s = mlp_check(batch, in_dim, hidden, out_dim);
+    if (s != QAOA_OK) return s;
+    if (!d_params || !d_x || !d_y || !d_act || !d_target || !d_grad || !d_loss)
+        return fail(QAOA_ERR_INVALID_ARG, "NULL pointer");
+    const MlpDims d{in_dim, hidden, out_dim};
+    const size_t need = mlp_scratch_bytes(batch, d);
+    if (need > MLP_STATIC_SCRATCH_BYTES)
+        return fail(QAOA_ERR_OUT_OF_RANGE, "batch %d needs %zu bytes of scratch, more than the %zu the library holds",
+                    batch, need, (size_t)MLP_STATIC_SCRATCH_BYTES);
+    void* scr = nullptr;
+    HIP_TRY(mlp_static_scratch(&scr));
+    // (no timing scope: it may create events)
+    HIP_TRY(launch_mlp_backward(batch, d, d_params, d_x, d_y, d_act, d_target, (float*)scr, d_grad, d_loss,
+                                (hipStream_t)stream));
+    return ok();
+}
+
 extern "C" qaoa_status_t qaoa_warm_angles(int32_t B, int32_t p, const float* d_y, const float* d_mu,
                                           const float* d_sd, double* d_theta, qaoa_stream_t stream)
 {

@@ -142,6 +142,10 @@ inline size_t mlp_scratch_bytes(int B, const MlpDims& d)
     return sizeof(float) * ((size_t)B * (2 * d.H + d.out) + 2) + sizeof(double) * (size_t)B + 8;
 }
 hipError_t launch_mlp_forward(int B, MlpDims d, const double* P, const float* X, float* Y, float* act, hipStream_t s);
+// the backward pass's device scratch for callers that cannot allocate (bytes)
+constexpr size_t MLP_STATIC_SCRATCH_BYTES = 8u << 20;
+// device address of that scratch on the current device (looked up once per device)
+hipError_t mlp_static_scratch(void** out);
 hipError_t launch_warm_angles(int B, int p, const float* Y, const float* mu, const float* sd, double* theta,
                               hipStream_t s);
 hipError_t launch_keep_better(int B, int p, const double* E_alt, const double* theta_alt, double* E, double* theta,

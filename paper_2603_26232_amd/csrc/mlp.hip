@@ -8,6 +8,8 @@
 // forward and backward arithmetic is FP32 with FP64 gradient accumulation.
 // Flat layout, row-major: W1[H][in], b1[H], W2[H][H], b2[H], W3[out][H],
 // b3[out]. Every reduction runs in a fixed order (bit-reproducible).
+#include <mutex>
+
 #include "common.h"
 
 namespace pq {
@@ -213,6 +215,35 @@ hipError_t launch_mlp_backward(int B, MlpDims d, const double* P, const float* X
     hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, B, d, X, act, delta, G);
     hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, B, d.out, sq, loss);
     return hipGetLastError();
+}
+
+// Scratch of the backward pass for callers that cannot allocate: a
+// file-scope device array (each device holds its own copy until the process
+// ends). Host code never passes the array's name to a kernel: its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+static __device__ __align__(256) uint8_t scratch[MLP_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t mlp_static_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace pq

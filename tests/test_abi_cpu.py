@@ -122,6 +122,16 @@ def test_warm_start_arguments_are_checked_on_the_host():
             assert ei.value.status == status, (fn.__name__, B, p, ptrs)
 
 
+def test_noalloc_backward_checks_its_scratch_limit_on_the_host():
+    # 9000 samples at 18 -> 128 -> 128 -> 6 need ~9.5 MB of scratch (limit 8 MiB)
+    with pytest.raises(_abi.QaoaError) as ei:
+        _abi.qaoa_mlp_backward_noalloc(9000, 18, 128, 6, 8, 8, 8, 8, 8, 8, 8, 0)
+    assert ei.value.status == 2 and "8388608" in str(ei.value)
+    with pytest.raises(_abi.QaoaError) as ei:
+        _abi.qaoa_mlp_backward_noalloc(10, 18, 128, 6, 8, 0, 8, 8, 8, 8, 8, 0)
+    assert ei.value.status == 1
+
+
 def test_predictor_file_shape():
     """The committed predictor holds plain arrays of an 18 -> 128 -> 128 -> 6
     network (loaded without pickle)."""
