@@ -90,6 +90,14 @@ typedef void* qaoa_stream_t;
 #define QAOA_FLAG_MIXER_MFMA_F32 0x8u
 #define QAOA_FLAG_MIXER_MFMA_BF16X3 0x10u
 #define QAOA_FLAG_MIXER_MFMA_BF16X4 0x20u
+/* Gradient memory. By default a QAOA_FLAG_GRADIENT batch keeps the state
+ * after every HBM pass of the forward sweep (for subgraphs of more than 13
+ * qubits: max_p (G - 1) stored states, G = the subgraph's qubit groups; with
+ * the default group split 2 for 14..20 qubits, 3 for 21..28, 4 above), so that the adjoint sweep reads psi
+ * where it needs it and writes only lambda. With QAOA_FLAG_GRADIENT_INPLACE
+ * the batch keeps one psi and the adjoint sweep rebuilds psi by undoing each
+ * pass (less memory, more HBM traffic); results are the same. */
+#define QAOA_FLAG_GRADIENT_INPLACE 0x40u
 
 /* Workspace size for a batch (paper Sec. 3.3: the subgraphs {G[V_i]} that
  * Alg. 1 produces, each solved by its own QAOA instance).

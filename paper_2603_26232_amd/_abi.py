@@ -22,6 +22,7 @@ QAOA_FLAG_SKIP_EDGELESS = 0x4
 QAOA_FLAG_MIXER_MFMA_F32 = 0x8
 QAOA_FLAG_MIXER_MFMA_BF16X3 = 0x10
 QAOA_FLAG_MIXER_MFMA_BF16X4 = 0x20
+QAOA_FLAG_GRADIENT_INPLACE = 0x40
 QAOA_MAX_QUBITS = 30
 QAOA_MAX_DEPTH = 32
 QAOA_MAX_K = 64

@@ -26,7 +26,7 @@ class QaoaBatch:
               "mfma_bf16x4": _abi.QAOA_FLAG_MIXER_MFMA_BF16X4}
 
     def __init__(self, sizes, sub_edges, max_p, max_k=16, gradient=False, raw_topk=False,
-                 skip_edgeless=False, device="cuda", stream=None, mixer="valu"):
+                 skip_edgeless=False, device="cuda", stream=None, mixer="valu", inplace_gradient=False):
         nq, off, u, v, w = batch_arrays(sizes, sub_edges)
         self.B = int(nq.shape[0])
         self.sizes = nq
@@ -34,7 +34,8 @@ class QaoaBatch:
         self.max_k = int(max_k)
         self.device = torch.device(device)
         flags = ((_abi.QAOA_FLAG_GRADIENT if gradient else 0) | (_abi.QAOA_FLAG_TOPK_RAW if raw_topk else 0)
-                 | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0) | self.MIXERS[mixer])
+                 | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0) | self.MIXERS[mixer]
+                 | (_abi.QAOA_FLAG_GRADIENT_INPLACE if inplace_gradient else 0))
         self.flags = flags
         nbytes = _abi.qaoa_workspace_bytes(self.B, nq, off, w, self.max_p, self.max_k, flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -191,6 +191,7 @@ struct Plan {
     int32_t B = 0, max_p = 0, max_k = 0;
     uint32_t flags = 0;
     int prec = 0;  // mixer block: 0 vector units, 1 FP32 MFMA, 2 / 3 BF16 split MFMA
+    bool ckpt = false;  // gradient checkpoints: one psi slot per forward pass
     std::vector<SubDesc> subs;
     int32_t total_tiles = 0;
     int64_t total_edges = 0;
@@ -259,7 +260,8 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     if (max_k < 1 || max_k > MAX_K) return fail(QAOA_ERR_OUT_OF_RANGE, "max_k = %d outside 1..%d", max_k, MAX_K);
     const uint32_t mixer =
         flags & (QAOA_FLAG_MIXER_MFMA_F32 | QAOA_FLAG_MIXER_MFMA_BF16X3 | QAOA_FLAG_MIXER_MFMA_BF16X4);
-    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS | mixer))
+    if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS | QAOA_FLAG_GRADIENT_INPLACE |
+                  mixer))
         return fail(QAOA_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if (mixer & (mixer - 1)) return fail(QAOA_ERR_INVALID_ARG, "at most one mixer precision mode may be set");
     if (mixer && (flags & QAOA_FLAG_GRADIENT))
@@ -273,6 +275,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
            : mixer == QAOA_FLAG_MIXER_MFMA_BF16X4 ? 3 : 0;
     P.subs.assign(B, SubDesc{});
     const bool grad = flags & QAOA_FLAG_GRADIENT;
+    P.ckpt = grad && !(flags & QAOA_FLAG_GRADIENT_INPLACE);
     int64_t tiles = 0;
     for (int b = 0; b < B; ++b) {
         const int n = nq[b];
@@ -382,7 +385,10 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
         lut_o += sizeof(float2) * (uint64_t)max_p * d.lut_len;
         d.edges = eo + sizeof(int32_t) * 3 * (uint64_t)eoff[b];
         if (d.skip) continue;  // closed form, nothing stored
-        d.psi = region(dim * sizeof(float2), 4096);
+        // with checkpoints, one psi slot per forward pass of the gradient
+        // sweep that precedes the fused turn: p (G - 1) at the largest depth
+        const uint64_t slots = (P.ckpt && d.ngroups >= 2) ? (uint64_t)max_p * (d.ngroups - 1) : 1;
+        d.psi = region(slots * dim * sizeof(float2), 4096);
         d.lam = grad ? region(dim * sizeof(float2), 4096) : 0;
         d.tab = region(dim * (uint64_t)d.tabw, 4096);
         d.tabB = d.ngroups >= 2 ? region(dim * (uint64_t)d.tabw, 4096) : 0;
@@ -727,9 +733,17 @@ static qaoa_status_t enqueue_grad_passes(qaoa_batch_t h, int32_t p, hipStream_t 
         const int nw = (int)c.work.size();
         std::vector<Op> ops = forward_ops(c.G, p);
         std::vector<PassOps> fwd = group_passes(ops);
-        for (size_t i = 0; i + 1 < fwd.size(); ++i) {
+        const int F = (int)fwd.size();
+        // with checkpoints, forward pass i writes psi slot i (reading slot
+        // i - 1), and the backward pass that undoes it reads slot i and
+        // stores only lambda; otherwise every pass works in slot 0 and the
+        // backward passes rebuild psi as they go
+        const bool ck = P.ckpt;
+        for (int i = 0; i + 1 < F; ++i) {
             PassOps o = fwd[i];
             o.init = i == 0;
+            o.psi_in = ck && i > 0 ? i - 1 : 0;
+            o.psi_out = ck ? i : 0;
             ProfScope ps(pass_name(o, false), st, pass_bytes(o, false, nw, c.tab_bytes));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, 0, st));
         }
@@ -739,14 +753,16 @@ static qaoa_status_t enqueue_grad_passes(qaoa_batch_t h, int32_t p, hipStream_t 
         // first backward pass (its inverse) share one kernel
         PassOps f = fwd.back();
         f.fused = 1;
+        f.psi_in = ck ? F - 2 : 0;
         {
             ProfScope ps(pass_name(f, true), st, pass_bytes(f, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[f.group], f, h->part, P.lut_max, st));
         }
-        for (size_t i = 1; i < bwd.size(); ++i) {
+        for (int i = 1; i < (int)bwd.size(); ++i) {
             PassOps o = bwd[i];
-            o.last = i + 1 == bwd.size();
-            o.nopsi = i + 2 == bwd.size();  // the last pass synthesises psi
+            o.last = i + 1 == (int)bwd.size();
+            o.nopsi = ck || i + 2 == (int)bwd.size();  // the last pass synthesises psi
+            o.psi_in = ck ? F - 1 - i : 0;
             ProfScope ps(pass_name(o, true), st, pass_bytes(o, true, nw, c.tab_bytes));
             HIP_TRY(launch_bwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, st));
         }

@@ -56,7 +56,16 @@ struct PassOps {
     int32_t fused;     // backward: forward RX(pre) + <C> + lambda = C psi first
     int32_t last;      // backward: the inverse of the first forward pass; nothing stored
     int32_t nopsi;     // backward: psi is not needed after this pass (not stored)
+    // psi slots: a forward pass reads slot psi_in and writes slot psi_out; a
+    // backward pass reads psi from slot psi_in (with gradient checkpoints
+    // every forward pass writes its own slot, which the backward pass that
+    // undoes it reads; otherwise everything stays in slot 0)
+    int32_t psi_in, psi_out;
 };
+
+// Bytes of one stored (symmetry-reduced) state of an n-qubit subgraph: one
+// psi slot.
+__host__ __device__ inline uint64_t state_bytes(int n) { return 8ull << (n - 1); }
 
 // Rotation parameters of one layer of one subgraph: e^{-i beta X} =
 // f (I - i t X) X^flip with (f, t) = (c, tan beta) (mode 0, |cos| >= |sin|,

@@ -727,7 +727,8 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     const uint32_t t = (uint32_t)wk.y;
     const int g = ops.group;
     const Geo geo = make_geo(sd, g, t);
-    float2* st = (float2*)(ws + sd->psi);
+    const float2* src = (const float2*)(ws + sd->psi + (uint64_t)ops.psi_in * state_bytes(sd->n));
+    float2* st = (float2*)(ws + sd->psi + (uint64_t)ops.psi_out * state_bytes(sd->n));
     const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
     const int lut_len = sd->lut_len;
     const CutTab tab = tile_tab(ws, sd, g, t);
@@ -752,7 +753,7 @@ __device__ __forceinline__ void fwd_pass_body(uint8_t* ws, const SubDesc* subs, 
     }
     if constexpr (KIND == F_LAST) load_cut_L<LE>(cr, tab, tid, m_end);
     float2 v[REGS];
-    if constexpr (KIND != F_FIRST) load_state<LS, CH == 3>(v, st, geo, tid);
+    if constexpr (KIND != F_FIRST) load_state<LS, CH == 3>(v, src, geo, tid);
     __syncthreads();  // phase table staged
     if constexpr (HAS_PRE) {
         seg_rot<CH, FULL, true, PREC>(v, lds, geo.c, pre.t, tid);
@@ -837,7 +838,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
     const uint32_t t = (uint32_t)wk.y;
     const int g = ops.group;
     const Geo geo = make_geo(sd, g, t);
-    float2* sp = (float2*)(ws + sd->psi);
+    float2* sp = (float2*)(ws + sd->psi + (uint64_t)ops.psi_in * state_bytes(sd->n));
     float2* sl = (float2*)(ws + sd->lam);
     const RxCoef* cf = (const RxCoef*)(ws + sd->coef);
     const int lut_len = sd->lut_len;
