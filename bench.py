@@ -48,7 +48,8 @@ sys.path.insert(0, ROOT)
 METRIC = "QAOA amp-updates/s + HBM GB/s; 2k-vertex solve time, learned vs plain angles"
 PASSES = [f"fwd_{k}_g{g}" for k in ("first", "single", "mid", "last") for g in range(4)] + \
     [f"bwd_{k}_g{g}" for k in ("fused", "single", "mid", "last", "single_nopsi", "mid_nopsi") for g in range(4)]
-KERNELS = PASSES + ["small", "cut_tables", "angle_prep", "reduce", "reduce_adam", "topk", "maxcut", "adam", "merge"]
+KERNELS = PASSES + ["small", "cut_tables", "angle_prep", "reduce", "reduce_adam", "topk", "maxcut", "adam", "merge",
+                    "mlp_forward", "warm_angles", "keep_better"]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -387,11 +388,12 @@ def main():
     if args.warmup:
         kern = read_profile()
         _abi.qaoa_profile_enable(0)
-    dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else (
-        "fwd_mid_g0" if args.workload == "precision26" else "bwd_mid_g0")
+    # without a warm-up the last timed step times every kernel instead
+    dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else None
     if args.graph:
         log("bench: Adam steps replay a captured HIP graph")
-    log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps (kernel events on {dom} only)")
+    log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps (kernel events on "
+        f"{dom or 'every kernel'} in the last)")
     # timed region: events only around the dominant kernel's launches, and
     # only in the last tenth of the steps (each event pair leaves a gap of a
     # few microseconds around the launch, ~3 % of a step when on every step);
@@ -410,6 +412,8 @@ def main():
     timed = read_profile()
     _abi.qaoa_profile_enable(0)
     _abi.qaoa_profile_select(None)
+    if dom is None:
+        dom = max(timed, key=lambda k: timed[k]["total_ms"])
     elapsed = t1 - t0
     ms_step = 1e3 * elapsed / args.steps
     value = W["updates"] * args.steps / elapsed

@@ -66,16 +66,32 @@ def tuned_splits():
 
 
 @pytest.mark.timeout(300)
-def test_gradient_24_qubits_tuned_split(tuned_splits):
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradient_24_qubits_tuned_split(tuned_splits, weighted):
+    """Unit weights, and weights 20..60 whose sum brings C(z) near the 2047
+    limit (the FP32 per-lane partial sums of the gradient terms then carry
+    the largest values)."""
     n, p = 24, 3
-    print(f"gradient parity: n={n}, p={p}, split {tuned_splits.get(n)}", flush=True)
     g = synth.erdos_renyi(n, 0.15, 2424)
-    edges = [(g.u, g.v, g.w)]
+    w = g.w
+    if weighted:
+        w = synth.random_weights(g.num_edges, 2426, 20, 60)
+        while w.sum() > 2047:
+            w = (w * 0.95).astype(np.int32)
+    print(f"gradient parity: n={n}, p={p}, split {tuned_splits.get(n)}, weight sum {int(w.sum())}", flush=True)
+    edges = [(g.u, g.v, w)]
     gamma, beta = synth.uniform_angles(2425, p, batch=1)
+    if weighted:  # small gammas keep the landscape smooth at these weights
+        gamma = gamma / 200.0
     bt = QaoaBatch([n], edges, max_p=p, max_k=4, gradient=True)
     E, dg, db = bt.expectation_grad(gamma, beta)
     torch.cuda.synchronize()
     ref = _grad_ref((n, edges[0], gamma[0], beta[0]))
+    e_ref, g_ref, b_ref = ref
+    rel = max(np.abs(dg.cpu().numpy()[0] - g_ref).max(), np.abs(db.cpu().numpy()[0] - b_ref).max()) / \
+        max(1.0, float(np.abs(np.concatenate([g_ref, b_ref])).max()))
+    print(f"  |E| {e_ref:.3f}, max |g| {np.abs(np.concatenate([g_ref, b_ref])).max():.3f}, "
+          f"gradient error / max(1, max|g|) = {rel:.2e}", flush=True)
     _check_grad(float(E[0]), dg.cpu().numpy()[0], db.cpu().numpy()[0], ref, n)
     bt.close()
 
