@@ -151,7 +151,9 @@ def workload_solve(args, name):
     cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
     log(f"bench: graph {g}, {part.M} subgraphs of sizes {min(part.size)}..{max(part.size)}, p={cfg.p}, "
         f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
-    S = Solver(g, part, cfg, skip_edgeless=skip, inplace_gradient=args.inplace_gradient)
+    S = Solver(g, part, cfg, skip_edgeless=skip, gradient_memory=args.gradient_memory)
+    from paper_2603_26232_amd import _abi
+    ckpt = _abi.qaoa_gradient_checkpoints(S.batch.handle)
     nE = np.array([len(e[0]) for e in S.sub_edges])
     act = nE > 0
     sim = [int(n) for n, e in zip(part.size, nE) if not (skip and e == 0)]
@@ -246,7 +248,7 @@ def workload_solve(args, name):
                                          f"final evaluation"}}
 
     config = {"workload": desc, "graph_replay": bool(args.graph), "merge_overlaps_next_solve": overlap,
-              "gradient_memory": "in place" if args.inplace_gradient else "forward checkpoints",
+              "gradient_memory": ("forward checkpoints" if ckpt else "in place") + f" ({args.gradient_memory})",
               "vertices": g.num_vertices, "edges": g.num_edges,
               "subgraphs": part.M, "simulated_subgraphs": len(sim),
               "qubits": [int(min(part.size)), int(max(part.size))],
@@ -319,8 +321,8 @@ def main():
     ap.add_argument("--latency-solves", type=int, default=3, help="single solves timed alone, per kind")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the Adam step from a captured HIP graph")
-    ap.add_argument("--inplace-gradient", action="store_true",
-                    help="keep one psi per subgraph; the adjoint sweep rebuilds it (default: forward checkpoints)")
+    ap.add_argument("--gradient-memory", choices=["auto", "checkpoints", "inplace"], default="auto",
+                    help="forward checkpoints, one psi rebuilt in place, or the library's choice by size")
     ap.add_argument("--tuning", default="default",
                     help="group-split tuning table (JSON from paper_2603_26232_amd.autotune); 'default' = the "
                          "package's table if present, 'none' = untuned")

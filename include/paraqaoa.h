@@ -90,14 +90,22 @@ typedef void* qaoa_stream_t;
 #define QAOA_FLAG_MIXER_MFMA_F32 0x8u
 #define QAOA_FLAG_MIXER_MFMA_BF16X3 0x10u
 #define QAOA_FLAG_MIXER_MFMA_BF16X4 0x20u
-/* Gradient memory. By default a QAOA_FLAG_GRADIENT batch keeps the state
- * after every HBM pass of the forward sweep (for subgraphs of more than 13
- * qubits: max_p (G - 1) stored states, G = the subgraph's qubit groups; with
- * the default group split 2 for 14..20 qubits, 3 for 21..28, 4 above), so that the adjoint sweep reads psi
- * where it needs it and writes only lambda. With QAOA_FLAG_GRADIENT_INPLACE
- * the batch keeps one psi and the adjoint sweep rebuilds psi by undoing each
- * pass (less memory, more HBM traffic); results are the same. */
+/* Gradient memory of a QAOA_FLAG_GRADIENT batch (results agree to rounding):
+ *   QAOA_FLAG_GRADIENT_CHECKPOINTS keeps the state after every HBM pass of
+ *     the forward sweep (for subgraphs of more than 13 qubits: max_p (G - 1)
+ *     stored states, G = the subgraph's qubit groups; with the default group
+ *     split 2 for 14..20 qubits, 3 for 21..28, 4 above), so that the adjoint
+ *     sweep reads psi where it needs it and writes only lambda;
+ *   QAOA_FLAG_GRADIENT_INPLACE keeps one psi, which the adjoint sweep
+ *     rebuilds by undoing each pass (less memory, 8 more bytes per stored
+ *     amplitude in each middle backward pass);
+ *   neither: checkpoints, unless the batch's states and cut tables fit the
+ *     256 MB Infinity Cache in place (224 MiB or less) but not with
+ *     checkpoints; then in place.
+ * Setting both is QAOA_ERR_INVALID_ARG. qaoa_gradient_checkpoints tells which
+ * a batch uses. */
 #define QAOA_FLAG_GRADIENT_INPLACE 0x40u
+#define QAOA_FLAG_GRADIENT_CHECKPOINTS 0x80u
 
 /* Workspace size for a batch (paper Sec. 3.3: the subgraphs {G[V_i]} that
  * Alg. 1 produces, each solved by its own QAOA instance).
@@ -328,6 +336,10 @@ qaoa_status_t qaoa_mlp_backward_noalloc(int32_t batch, int32_t in_dim, int32_t h
                                         const double* d_params, const float* d_x, const float* d_y,
                                         const float* d_act, const float* d_target, double* d_grad, double* d_loss,
                                         qaoa_stream_t stream);
+
+/* *out = 1 if the batch keeps forward checkpoints for its gradient (see
+ * QAOA_FLAG_GRADIENT_CHECKPOINTS), else 0. */
+qaoa_status_t qaoa_gradient_checkpoints(qaoa_batch_t h, int32_t* out);
 
 /* Where subgraph b's state lives: the byte offset, inside the workspace, of
  * its stored amplitudes. The ansatz state is invariant under flipping every

@@ -23,6 +23,7 @@ QAOA_FLAG_MIXER_MFMA_F32 = 0x8
 QAOA_FLAG_MIXER_MFMA_BF16X3 = 0x10
 QAOA_FLAG_MIXER_MFMA_BF16X4 = 0x20
 QAOA_FLAG_GRADIENT_INPLACE = 0x40
+QAOA_FLAG_GRADIENT_CHECKPOINTS = 0x80
 QAOA_MAX_QUBITS = 30
 QAOA_MAX_DEPTH = 32
 QAOA_MAX_K = 64
@@ -81,6 +82,7 @@ def lib() -> ct.CDLL:
             "qaoa_warm_angles": [_i32, _i32, _vp, _vp, _vp, _vp, _vp],
             "qaoa_keep_better": [_i32, _i32, _vp, _vp, _vp, _vp, _vp],
             "qaoa_state_offset": [_vp, _i32, _vp],
+            "qaoa_gradient_checkpoints": [_vp, _vp],
             "qaoa_profile_enable": [_i32],
             "qaoa_profile_read": [ct.c_char_p, _vp, _vp, _vp],
             "qaoa_profile_select": [ct.c_char_p],
@@ -244,6 +246,12 @@ def qaoa_mlp_backward_noalloc(batch, in_dim, hidden, out_dim, d_params, d_x, d_y
                               d_loss, stream) -> None:
     _call("qaoa_mlp_backward_noalloc", batch, in_dim, hidden, out_dim, _vp(d_params), _vp(d_x), _vp(d_y),
           _vp(d_act), _vp(d_target), _vp(d_grad), _vp(d_loss), _vp(stream))
+
+
+def qaoa_gradient_checkpoints(h: int) -> bool:
+    out = ct.c_int32(0)
+    _call("qaoa_gradient_checkpoints", _vp(h), ct.byref(out))
+    return bool(out.value)
 
 
 def qaoa_state_offset(h: int, b: int) -> int:

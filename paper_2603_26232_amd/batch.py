@@ -24,9 +24,12 @@ class QaoaBatch:
 
     MIXERS = {"valu": 0, "mfma_f32": _abi.QAOA_FLAG_MIXER_MFMA_F32, "mfma_bf16x3": _abi.QAOA_FLAG_MIXER_MFMA_BF16X3,
               "mfma_bf16x4": _abi.QAOA_FLAG_MIXER_MFMA_BF16X4}
+    # gradient memory: the library's choice, forward checkpoints, or one psi rebuilt in place
+    GRADIENT_MEMORY = {"auto": 0, "checkpoints": _abi.QAOA_FLAG_GRADIENT_CHECKPOINTS,
+                       "inplace": _abi.QAOA_FLAG_GRADIENT_INPLACE}
 
     def __init__(self, sizes, sub_edges, max_p, max_k=16, gradient=False, raw_topk=False,
-                 skip_edgeless=False, device="cuda", stream=None, mixer="valu", inplace_gradient=False):
+                 skip_edgeless=False, device="cuda", stream=None, mixer="valu", gradient_memory="auto"):
         nq, off, u, v, w = batch_arrays(sizes, sub_edges)
         self.B = int(nq.shape[0])
         self.sizes = nq
@@ -35,7 +38,7 @@ class QaoaBatch:
         self.device = torch.device(device)
         flags = ((_abi.QAOA_FLAG_GRADIENT if gradient else 0) | (_abi.QAOA_FLAG_TOPK_RAW if raw_topk else 0)
                  | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0) | self.MIXERS[mixer]
-                 | (_abi.QAOA_FLAG_GRADIENT_INPLACE if inplace_gradient else 0))
+                 | self.GRADIENT_MEMORY[gradient_memory])
         self.flags = flags
         nbytes = _abi.qaoa_workspace_bytes(self.B, nq, off, w, self.max_p, self.max_k, flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -216,6 +216,11 @@ struct Plan {
     std::vector<Class> classes;
 };
 
+// MI355X's Infinity Cache (the memory-side last-level cache) and the share
+// of it a batch's live states may take to count as cache-resident
+constexpr uint64_t CACHE_BYTES = 256ull << 20;
+constexpr uint64_t CACHE_FIT_BYTES = 224ull << 20;
+
 // layout-chain code of group g (see launch_fwd_pass): 3 for group 0; for a
 // high group 2 (8 qubits), 4 (5..7), 1 (4), 5 (1..3)
 int chain_of(const SubDesc& d, int g)
@@ -261,8 +266,10 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     const uint32_t mixer =
         flags & (QAOA_FLAG_MIXER_MFMA_F32 | QAOA_FLAG_MIXER_MFMA_BF16X3 | QAOA_FLAG_MIXER_MFMA_BF16X4);
     if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS | QAOA_FLAG_GRADIENT_INPLACE |
-                  mixer))
+                  QAOA_FLAG_GRADIENT_CHECKPOINTS | mixer))
         return fail(QAOA_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    if ((flags & QAOA_FLAG_GRADIENT_INPLACE) && (flags & QAOA_FLAG_GRADIENT_CHECKPOINTS))
+        return fail(QAOA_ERR_INVALID_ARG, "QAOA_FLAG_GRADIENT_INPLACE and QAOA_FLAG_GRADIENT_CHECKPOINTS together");
     if (mixer & (mixer - 1)) return fail(QAOA_ERR_INVALID_ARG, "at most one mixer precision mode may be set");
     if (mixer && (flags & QAOA_FLAG_GRADIENT))
         return fail(QAOA_ERR_NOT_SUPPORTED, "the matrix-core mixer modes have no gradient path");
@@ -275,7 +282,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
            : mixer == QAOA_FLAG_MIXER_MFMA_BF16X4 ? 3 : 0;
     P.subs.assign(B, SubDesc{});
     const bool grad = flags & QAOA_FLAG_GRADIENT;
-    P.ckpt = grad && !(flags & QAOA_FLAG_GRADIENT_INPLACE);
+    P.ckpt = false;  // decided once the subgraphs are known
     int64_t tiles = 0;
     for (int b = 0; b < B; ++b) {
         const int n = nq[b];
@@ -320,6 +327,23 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     if (tiles > (1ll << 30)) return fail(QAOA_ERR_OUT_OF_RANGE, "batch too large (%lld tiles)", (long long)tiles);
     P.total_tiles = (int32_t)tiles;
     P.total_edges = eoff[B];
+    if (grad) {
+        // Gradient memory: checkpoints unless asked otherwise, except when the
+        // single-slot states and tables fit the 256 MB Infinity Cache and the
+        // checkpoints would not (there the cache serves the adjoint sweep's
+        // re-reads of psi faster than HBM serves the checkpoints)
+        uint64_t inplace = 0, ckpt = 0;
+        for (const SubDesc& d : P.subs) {
+            if (d.skip) continue;
+            const uint64_t st = state_bytes(d.n), tb = (1ull << (d.n - 1)) * d.tabw * (d.ngroups >= 2 ? 2 : 1);
+            const uint64_t slots = d.ngroups >= 2 ? (uint64_t)max_p * (d.ngroups - 1) : 1;
+            inplace += 2 * st + tb;
+            ckpt += (slots + 1) * st + tb;
+        }
+        if (flags & QAOA_FLAG_GRADIENT_INPLACE) P.ckpt = false;
+        else if (flags & QAOA_FLAG_GRADIENT_CHECKPOINTS) P.ckpt = true;
+        else P.ckpt = !(inplace <= CACHE_FIT_BYTES && ckpt > CACHE_BYTES);
+    }
 
     // work lists: every tile (tables, top-k); per group-count class (passes)
     P.work_all.reserve(tiles);
@@ -860,6 +884,13 @@ extern "C" qaoa_status_t maxcut_eval(int32_t num_vertices, int64_t num_edges, co
     ProfScope ps("maxcut", st, (double)num_edges * (d_w ? 12.0 : 8.0) * (num_assign > 0 ? 1.0 : 0.0) +
                                    4.0 * num_assign * ((num_vertices + 31) / 32) + 8.0 * num_assign);
     HIP_TRY(launch_maxcut_eval(num_vertices, num_edges, d_u, d_v, d_w, num_assign, d_assign, d_cut, st));
+    return ok();
+}
+
+extern "C" qaoa_status_t qaoa_gradient_checkpoints(qaoa_batch_t h, int32_t* out)
+{
+    if (!h || !out) return fail(QAOA_ERR_INVALID_ARG, "NULL argument");
+    *out = h->P.ckpt ? 1 : 0;
     return ok();
 }
 

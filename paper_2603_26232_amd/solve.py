@@ -53,7 +53,7 @@ class Solver:
     nothing new (the bench times `run`)."""
 
     def __init__(self, graph, part: Partition, cfg: SolveConfig, device="cuda", skip_edgeless=False,
-                 inplace_gradient=False):
+                 gradient_memory="auto"):
         self.g = graph
         self.part = part
         self.cfg = cfg
@@ -62,7 +62,7 @@ class Solver:
         self.B = part.M
         dev = self.device
         self.batch = QaoaBatch(part.size, self.sub_edges, max_p=cfg.p, max_k=cfg.k, gradient=True,
-                               skip_edgeless=skip_edgeless, device=dev, inplace_gradient=inplace_gradient)
+                               skip_edgeless=skip_edgeless, device=dev, gradient_memory=gradient_memory)
         P = self.B * cfg.p
         self.theta = torch.zeros(2 * P, dtype=torch.float64, device=dev)   # [gamma | beta]
         self._theta_host = torch.zeros(2 * P, dtype=torch.float64, pin_memory=dev.type == "cuda")

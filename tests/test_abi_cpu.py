@@ -54,7 +54,7 @@ def test_argument_errors():
         _ws([5], [e], max_k=65)
     assert ei.value.status == 2
     with pytest.raises(_abi.QaoaError) as ei:
-        _ws([5], [e], flags=0x80)
+        _ws([5], [e], flags=0x100)  # an unknown flag bit
     assert ei.value.status == 1
     heavy = (np.array([0], np.int32), np.array([1], np.int32), np.array([5000], np.int32))
     with pytest.raises(_abi.QaoaError) as ei:
@@ -109,6 +109,30 @@ def test_adam_arguments_are_checked_on_the_host():
         with pytest.raises(_abi.QaoaError) as ei:
             _abi.qaoa_adam_step(*args, 1, 0)
         assert ei.value.status == status, args
+
+
+def test_gradient_memory_choice():
+    """Forward checkpoints unless the single-slot states fit the 256 MB cache
+    and the checkpoints would not: the 400-vertex batch (21 x 20 qubits,
+    ~200 MB in place, ~370 MB with checkpoints) stays in place, the
+    2000-vertex ragged batch takes checkpoints; both flags are rejected."""
+    G, IP, CK = 0x1, 0x40, 0x80
+
+    def ws(sizes, edges, flags):
+        nq, off, u, v, w = batch_arrays(sizes, edges)
+        return _abi.qaoa_workspace_bytes(len(nq), nq, off, w, 3, 16, flags)
+
+    g = synth.erdos_renyi(400, 0.05, 0)
+    part = partition_equal(400, 20)
+    se, _ = bucket_edges(part, g.u, g.v, g.w)
+    assert ws(part.size, se, G) == ws(part.size, se, G | IP) < ws(part.size, se, G | CK)
+    g = synth.erdos_renyi(2000, 0.01, 0)
+    part = partition_chain(2000, synth.ragged_sizes(1, 14, 26, 2000))
+    se, _ = bucket_edges(part, g.u, g.v, g.w)
+    assert ws(part.size, se, G | 0x4) == ws(part.size, se, G | 0x4 | CK) > ws(part.size, se, G | 0x4 | IP)
+    with pytest.raises(_abi.QaoaError) as ei:
+        ws(part.size, se, G | IP | CK)
+    assert ei.value.status == 1
 
 
 def test_warm_start_arguments_are_checked_on_the_host():

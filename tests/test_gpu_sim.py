@@ -195,15 +195,17 @@ def test_topk(sizes, k, raw):
     bt.close()
 
 
-@pytest.mark.parametrize("inplace", [False, True])
+@pytest.mark.parametrize("memory", ["checkpoints", "inplace"])
 @pytest.mark.parametrize("sizes,p,seed", [([6], 1, 0), ([12], 2, 1), ([13, 16], 3, 2), ([20], 3, 3),
                                           ([21, 12, 7], 2, 4), ([22], 3, 5), ([20, 21], 4, 6), ([16, 21], 1, 7)])
-def test_gradient(sizes, p, seed, inplace):
+def test_gradient(sizes, p, seed, memory):
     """Both gradient memory modes: checkpoints of every forward pass (the
     adjoint sweep reads psi) and in place (the sweep rebuilds psi)."""
     edges = _subgraphs(sizes, 300 + seed, p_edge=0.3, weighted=seed % 2 == 1)
     gamma, beta = synth.uniform_angles(900 + seed, p, batch=len(sizes))
-    bt = QaoaBatch(sizes, edges, max_p=p, max_k=4, gradient=True, inplace_gradient=inplace)
+    bt = QaoaBatch(sizes, edges, max_p=p, max_k=4, gradient=True, gradient_memory=memory)
+    from paper_2603_26232_amd import _abi
+    assert _abi.qaoa_gradient_checkpoints(bt.handle) == (memory == "checkpoints")
     E, dg, db = bt.expectation_grad(gamma, beta)
     E, dg, db = E.cpu().numpy(), dg.cpu().numpy(), db.cpu().numpy()
     for b, n in enumerate(sizes):
