@@ -75,7 +75,11 @@ def _declare(L):
     L.or_expectation.restype = ct.c_double
     L.or_expectation.argtypes = [ct.c_int32, _c128p, _i64p]
     L.or_topk.restype = ct.c_int32
-    L.or_topk.argtypes = [ct.c_int32, _c128p, ct.c_int32, ct.c_int32, _u32p, _f64p]
+    L.or_topk.argtypes = [ct.c_int32, _c128p, ct.c_int32, ct.c_int32, ct.c_uint32, _u32p, _f64p]
+    L.or_tie_rank.restype = ct.c_uint64
+    L.or_tie_rank.argtypes = [ct.c_uint64, ct.c_int32]
+    L.or_free_mask.restype = ct.c_uint32
+    L.or_free_mask.argtypes = [ct.c_int32, ct.c_int64, _i32p, _i32p, ct.c_void_p]
     L.or_gradient.restype = None
     L.or_gradient.argtypes = [ct.c_int32, _i64p, ct.c_int32, _f64p, _f64p, ct.c_void_p, _f64p, _f64p]
     L.or_cold_start.restype = None
@@ -191,11 +195,26 @@ def expectation(n, psi, C) -> float:
                                       np.ascontiguousarray(C, dtype=np.int64)))
 
 
-def topk(n, psi, k, canonical=True):
-    """Top-k by probability (Sec. 3.3.2); returns (idx uint32[k], prob float64[k], k_eff)."""
+def free_mask(n, u, v, w=None) -> int:
+    """Vertices without an edge of positive weight inside the subgraph (bit j
+    = local vertex j): the state is exactly invariant under flipping them."""
+    u, v = _i32(u), _i32(v)
+    wa, wp = _wptr(w)
+    return int(lib().or_free_mask(n, u.shape[0], u, v, wp))
+
+
+def tie_rank(x, m) -> int:
+    """Rank of index x inside a tie group of 2^m strings (or_topk's order)."""
+    return int(lib().or_tie_rank(int(x), int(m)))
+
+
+def topk(n, psi, k, canonical=True, free=0):
+    """Top-k by probability (Sec. 3.3.2) with the tie order of or_topk (tie
+    groups from the free-vertex mask `free`, see free_mask); returns
+    (idx uint32[k], prob float64[k], k_eff)."""
     idx = np.zeros(k, dtype=np.uint32)
     prob = np.zeros(k, dtype=np.float64)
-    ke = lib().or_topk(n, np.ascontiguousarray(psi, dtype=np.complex128), k, int(canonical), idx, prob)
+    ke = lib().or_topk(n, np.ascontiguousarray(psi, dtype=np.complex128), k, int(canonical), int(free), idx, prob)
     return idx, prob, int(ke)
 
 

@@ -205,37 +205,139 @@ double or_expectation(int32_t n, const cplx* psi, const int64_t* C)
     return e;
 }
 
+/* Free vertices of a subgraph: those without an edge of positive weight
+ * inside it (bit j of the result for local vertex j). Flipping the bit of a
+ * free vertex leaves C(z) unchanged, so its qubit stays in |+> through every
+ * layer (|+> is an eigenvector of X, and U_C does not act on it): the state
+ * is exactly invariant under that flip. */
+uint32_t or_free_mask(int32_t n, int64_t ne, const int32_t* u, const int32_t* v, const int32_t* w)
+{
+    uint32_t busy = 0;
+    for (int64_t e = 0; e < ne; ++e)
+        if (weight_of(w, e) > 0) busy |= (1u << u[e]) | (1u << v[e]);
+    uint32_t all = (n >= 32) ? 0xFFFFFFFFu : ((1u << n) - 1u);
+    return all & ~busy;
+}
+
+/* Order of the strings inside a tie group: a bijection of [0, 2^m) built
+ * from Marsaglia's xorshift step g(x) = x XOR (x >> s), s = ceil(m/2) (its
+ * own inverse on m bits), and Knuth's multiplicative hashing by the odd
+ * constant 2654435761 (2^32 / golden ratio): rank(x) = g(2654435761 g(x)
+ * mod 2^m). Both steps are bijections, so ranks are distinct. */
+static uint64_t xs_step(uint64_t x, int m)
+{
+    return x ^ (x >> ((m + 1) / 2));
+}
+
+static uint64_t hash_rank(uint64_t x, int m)
+{
+    if (m <= 0) return 0;
+    uint64_t mask = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
+    return xs_step((xs_step(x, m) * 2654435761ull) & mask, m);
+}
+
+/* rank of index x among the 2^m strings of a tie group (exported for tests) */
+uint64_t or_tie_rank(uint64_t x, int32_t m)
+{
+    return hash_rank(x, m);
+}
+
+/* the bits of x at the positions of mask, packed to the low end */
+static uint64_t gather_bits(uint64_t x, uint32_t mask)
+{
+    uint64_t out = 0;
+    int k = 0;
+    for (int j = 0; j < 32; ++j)
+        if (mask & (1u << j)) {
+            out |= ((x >> j) & 1ull) << k;
+            ++k;
+        }
+    return out;
+}
+
+typedef struct {
+    double pr;      /* probability of the tie group (that of its representative) */
+    uint64_t rep;   /* the group's representative */
+    uint64_t rank;  /* hash rank of the string inside its group */
+    uint64_t z;
+} topk_entry;
+
+/* (pr desc, rep asc, rank asc) */
+static int topk_before(const topk_entry* a, const topk_entry* b)
+{
+    if (a->pr != b->pr) return a->pr > b->pr;
+    if (a->rep != b->rep) return a->rep < b->rep;
+    return a->rank < b->rank;
+}
+
 /* Selective Distribution Exploration (Sec. 3.3.2): the K most probable
  * bitstrings, pi(z) = |psi(z)|^2 from the full distribution. With
  * `canonical` set only z whose bit 0 is 0 are candidates (pi(z) equals
  * pi(complement z) exactly, so this keeps one of each complement pair).
- * Order: pi descending, ties by z ascending. Returns K_eff = min(k, #cand);
- * the remaining rows of idx/prob are filled with UINT32_MAX / -1. */
-int32_t or_topk(int32_t n, const cplx* psi, int32_t k, int32_t canonical, uint32_t* idx,
+ *
+ * Ties (the paper does not order equal probabilities). Besides the
+ * complement, pi is exactly invariant under flipping the bit of any free
+ * vertex (free_mask, see or_free_mask). The candidates that these moves
+ * connect form a tie group of equal probability:
+ *   Fm = the free vertices other than vertex 0 in canonical mode, all free
+ *        vertices in raw mode;
+ *   the partner move complements every bit and, in canonical mode, flips
+ *        bit 0 back; it stays inside the candidates in raw mode, and in
+ *        canonical mode when vertex 0 is free;
+ *   r(z) = z with the bits of Fm cleared; if the partner move applies and
+ *        the subgraph has a vertex that is not free, the group has two
+ *        halves {r ^ S}, {r' ^ S} (S over Fm, r' = r of the partner) and its
+ *        representative is min(r, r'); else one half and r itself.
+ * A string's index inside its group is x = (bits of z at Fm, packed) with
+ * the half as an extra low bit when there are two halves (m bits), and its
+ * rank is hash_rank(x, m). Order: the group's probability (that of its
+ * representative) descending, representative ascending, rank ascending.
+ * Returns K_eff = min(k, #cand); the remaining rows of idx/prob are filled
+ * with UINT32_MAX / -1. */
+int32_t or_topk(int32_t n, const cplx* psi, int32_t k, int32_t canonical, uint32_t free_mask, uint32_t* idx,
                 double* prob)
 {
     uint64_t dim = 1ull << n;
+    uint64_t all = dim - 1ull;
+    uint32_t fm = canonical ? (free_mask & ~1u) : free_mask;
+    int partner_ok = canonical ? (int)(free_mask & 1u) : 1;
+    int halves = (partner_ok && (uint64_t)free_mask != all) ? 2 : 1;
+    int m = __builtin_popcount(fm) + (halves == 2 ? 1 : 0);
+    topk_entry* top = (topk_entry*)malloc((size_t)(k > 0 ? k : 1) * sizeof(topk_entry));
     int32_t have = 0;
-    for (int32_t r = 0; r < k; ++r) {
-        idx[r] = UINT32_MAX;
-        prob[r] = -1.0;
-    }
     for (uint64_t z = 0; z < dim; ++z) {
         if (canonical && (z & 1)) continue;
-        double pr = creal(psi[z]) * creal(psi[z]) + cimag(psi[z]) * cimag(psi[z]);
-        /* find the insertion point: first r whose entry ranks below (pr, z) */
-        int32_t r = have;
-        while (r > 0 && (prob[r - 1] < pr || (prob[r - 1] == pr && idx[r - 1] > z))) --r;
-        if (r >= k) continue;
-        int32_t last = (have < k) ? have : k - 1;
-        for (int32_t q = last; q > r; --q) {
-            idx[q] = idx[q - 1];
-            prob[q] = prob[q - 1];
+        topk_entry e;
+        uint64_t r = z & ~(uint64_t)fm;
+        uint64_t half = 0;
+        e.rep = r;
+        if (halves == 2) {
+            uint64_t pz = canonical ? ((~z & all) ^ 1ull) : (~z & all);
+            uint64_t r2 = pz & ~(uint64_t)fm;
+            if (r2 < r) {
+                e.rep = r2;
+                half = 1;
+            }
         }
-        idx[r] = (uint32_t)z;
-        prob[r] = pr;
+        uint64_t x = gather_bits(z, fm);
+        if (halves == 2) x = (x << 1) | half;
+        e.rank = hash_rank(x, m);
+        e.pr = creal(psi[e.rep]) * creal(psi[e.rep]) + cimag(psi[e.rep]) * cimag(psi[e.rep]);
+        e.z = z;
+        /* insertion into the sorted top list */
+        int32_t pos = have;
+        while (pos > 0 && topk_before(&e, &top[pos - 1])) --pos;
+        if (pos >= k) continue;
+        int32_t last = (have < k) ? have : k - 1;
+        for (int32_t q = last; q > pos; --q) top[q] = top[q - 1];
+        top[pos] = e;
         if (have < k) ++have;
     }
+    for (int32_t q = 0; q < k; ++q) {
+        idx[q] = q < have ? (uint32_t)top[q].z : UINT32_MAX;
+        prob[q] = q < have ? top[q].pr : -1.0;
+    }
+    free(top);
     return have;
 }
 
@@ -359,7 +461,9 @@ void or_eval_batch(int32_t B, const int32_t* nq, const int64_t* eoff, const int3
         or_cut_table(n, ne, u + e0, v + e0, w ? w + e0 : NULL, C);
         or_qaoa_state(n, C, p, gamma + (int64_t)b * p, beta + (int64_t)b * p, psi);
         E[b] = or_expectation(n, psi, C);
-        if (k > 0) or_topk(n, psi, k, canonical, idx + (int64_t)b * k, prob + (int64_t)b * k);
+        if (k > 0)
+            or_topk(n, psi, k, canonical, or_free_mask(n, ne, u + e0, v + e0, w ? w + e0 : NULL),
+                    idx + (int64_t)b * k, prob + (int64_t)b * k);
         free(C);
         free(psi);
     }
@@ -385,7 +489,9 @@ void or_solve_batch(int32_t B, const int32_t* nq, const int64_t* eoff, const int
         or_adam_solve(n, C, p, T, lr, b1, b2, eps, g, be, NULL);
         or_qaoa_state(n, C, p, g, be, psi);
         E[b] = or_expectation(n, psi, C);
-        if (k > 0) or_topk(n, psi, k, canonical, idx + (int64_t)b * k, prob + (int64_t)b * k);
+        if (k > 0)
+            or_topk(n, psi, k, canonical, or_free_mask(n, ne, u + e0, v + e0, w ? w + e0 : NULL),
+                    idx + (int64_t)b * k, prob + (int64_t)b * k);
         free(C);
         free(psi);
     }

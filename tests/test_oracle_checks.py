@@ -8,7 +8,7 @@
    planted back into a copy of oracle.c and the sanitizer run must catch it.
 3. Planted mistakes: copies of oracle.c with one plausible error each (a
    dropped term, a wrong sign, swapped operands, a stale optimiser moment,
-   a wrong tie order) must each fail the pin suite. This shows that the pins
+   a wrong tie order or tie group) must each fail the pin suite. This shows that the pins
    fix every part of the oracle the GPU path is compared with.
 """
 import os
@@ -111,7 +111,11 @@ MUTANTS = [
     ("cut_table_unit_weight", "if (((z >> u[e]) & 1) != ((z >> v[e]) & 1)) c += weight_of(w, e);",
      "if (((z >> u[e]) & 1) != ((z >> v[e]) & 1)) c += 1;", 0),
     ("cutval_unit_weight", "if (x[u[e]] != x[v[e]]) cut += weight_of(w, e);", "if (x[u[e]] != x[v[e]]) cut += 1;", 0),
-    ("topk_tie_order", "idx[r - 1] > z", "idx[r - 1] < z", 0),
+    ("topk_tie_group_order", "if (a->rep != b->rep) return a->rep < b->rep;",
+     "if (a->rep != b->rep) return a->rep > b->rep;", 0),
+    ("topk_tie_rank_order", "return a->rank < b->rank;", "return a->rank > b->rank;", 0),
+    ("topk_tie_rank_unmixed", "return xs_step((xs_step(x, m) * 2654435761ull) & mask, m);", "return x & mask;", 0),
+    ("free_vertex_zero_weight", "if (weight_of(w, e) > 0) busy", "if (weight_of(w, e) >= 0) busy", 0),
     ("merge_orientation_ignored", "int32_t o = (int32_t)((b & 1u) ^ q->x[start[lvl]]);",
      "int32_t o = (int32_t)(b & 1u);", 0),
     ("merge_tie_order", "return a->digits[i] < b->digits[i] ? -1 : 1;",

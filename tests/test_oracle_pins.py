@@ -271,6 +271,103 @@ def test_topk_against_full_sort():
     assert ke == 2 and idx[2] == oracle.UINT32_MAX and prob[3] == -1.0
 
 
+def test_free_vertices_leave_the_state_invariant():
+    """A vertex without an edge inside the subgraph keeps its qubit in |+>:
+    psi(z) = psi(z ^ 2^j) exactly for it, and not for the others."""
+    n = 7
+    u, v = _edges([(0, 2), (2, 5), (5, 0), (1, 5)])  # vertices 3, 4, 6 free
+    w = np.array([2, 1, 3, 1], np.int32)
+    assert oracle.free_mask(n, u, v, w) == (1 << 3) | (1 << 4) | (1 << 6)
+    assert oracle.free_mask(n, u, v, np.array([2, 1, 3, 0], np.int32)) == (1 << 1) | (1 << 3) | (1 << 4) | (1 << 6)
+    C = oracle.cut_table(n, u, v, w)
+    gam, bet = synth.uniform_angles(41, 3)
+    psi = oracle.qaoa_state(n, C, gam[0], bet[0])
+    z = np.arange(1 << n)
+    for j in range(n):
+        d = np.max(np.abs(psi - psi[z ^ (1 << j)]))
+        if j in (3, 4, 6):
+            assert d <= 1e-15, j
+        else:
+            assert d > 1e-6, j
+
+
+def test_tie_rank_is_a_bijection():
+    for m in range(0, 15):
+        ranks = [oracle.tie_rank(x, m) for x in range(1 << m)]
+        assert sorted(ranks) == list(range(1 << m)), m
+
+
+def _tie_groups(n, free, canonical):
+    """Tie groups by closure: strings connected by flipping a free bit (not
+    bit 0 in canonical mode) or by the complement (with bit 0 flipped back in
+    canonical mode, allowed there only when vertex 0 is free)."""
+    full = (1 << n) - 1
+    cand = [z for z in range(1 << n) if not (canonical and z & 1)]
+    moves = [1 << j for j in range(n) if free >> j & 1 and not (canonical and j == 0)]
+    part = (lambda z: (~z & full) ^ 1) if canonical else (lambda z: ~z & full)
+    part_ok = (free & 1) if canonical else True
+    group = {}
+    for z0 in cand:
+        if z0 in group:
+            continue
+        orbit, todo = {z0}, [z0]
+        while todo:
+            z = todo.pop()
+            nxt = [z ^ mv for mv in moves] + ([part(z)] if part_ok else [])
+            for y in nxt:
+                if y not in orbit:
+                    orbit.add(y)
+                    todo.append(y)
+        for y in orbit:
+            group[y] = frozenset(orbit)
+    return cand, group
+
+
+@pytest.mark.parametrize("canonical", [True, False])
+@pytest.mark.parametrize("edges,n,seed", [([(0, 1)], 6, 1), ([(1, 2), (2, 4)], 7, 2), ([(0, 3)], 5, 3), ([], 5, 4),
+                                          ([(0, 1), (1, 2), (2, 0), (3, 4)], 5, 5)])
+def test_topk_ties_by_groups(edges, n, seed, canonical):
+    """The top-k list runs through tie groups (found by closure) in order of
+    their probability and then of their smallest member; inside a group it
+    lists distinct members; a group is finished before the next starts."""
+    u, v = _edges(edges)
+    free = oracle.free_mask(n, u, v)
+    C = oracle.cut_table(n, u, v)
+    gam, bet = synth.uniform_angles(seed, 2)
+    psi = oracle.qaoa_state(n, C, gam[0], bet[0])
+    pr = np.abs(psi) ** 2
+    cand, group = _tie_groups(n, free, canonical)
+    # probabilities are constant on a group
+    for z in cand:
+        assert all(abs(pr[y] - pr[z]) <= 1e-15 for y in group[z])
+    order = sorted(set(group[z] for z in cand), key=lambda gset: (-pr[min(gset)], min(gset)))
+    k = min(24, len(cand))
+    idx, prob, ke = oracle.topk(n, psi, k, canonical, free)
+    assert ke == k and len(set(idx.tolist())) == k
+    expect_groups, left = [], k
+    for gset in order:
+        if left <= 0:
+            break
+        expect_groups += [gset] * min(len(gset), left)
+        left -= len(gset)
+    for z, gset, p in zip(idx, expect_groups, prob):
+        assert int(z) in gset and p == pytest.approx(pr[min(gset)], abs=1e-15)
+
+
+def test_topk_tie_order_worked_example():
+    """Hand-worked order inside a tie group (tests/golden/topk_tie_example.json)."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "topk_tie_example.json")))
+    n = g["n"]
+    u, v = _edges([tuple(e) for e in g["edges"]])
+    C = oracle.cut_table(n, u, v)
+    psi = oracle.qaoa_state(n, C, [math.pi / 2], [math.pi / 8])
+    free = oracle.free_mask(n, u, v)
+    idx, prob, ke = oracle.topk(n, psi, 4, False, free)
+    assert list(idx) == g["top4_raw"] and np.allclose(prob, 1 / 32, atol=1e-15)
+    idx, prob, ke = oracle.topk(n, psi, 4, True, free)
+    assert list(idx) == g["top4_canonical"]
+
+
 # ---------------------------------------------------------------- gradient
 @pytest.mark.parametrize("n,p,seed", [(6, 1, 0), (8, 3, 1), (10, 2, 2), (7, 4, 3)])
 def test_adjoint_gradient_matches_central_differences(n, p, seed):
@@ -420,7 +517,7 @@ def test_eval_batch_equals_per_subgraph_functions(canonical):
         C = oracle.cut_table(n, u, v, w)
         psi = oracle.qaoa_state(n, C, gamma[b], beta[b])
         assert E[b] == oracle.expectation(n, psi, C)
-        oi, op, ke = oracle.topk(n, psi, k, canonical=canonical)
+        oi, op, ke = oracle.topk(n, psi, k, canonical=canonical, free=oracle.free_mask(n, u, v, w))
         assert np.array_equal(idx[b], oi) and np.array_equal(prob[b], op)
 
 
@@ -435,7 +532,7 @@ def test_solve_batch_equals_per_subgraph_functions():
         assert np.array_equal(gf[b], g) and np.array_equal(bf[b], be)
         psi = oracle.qaoa_state(n, C, g, be)
         assert E[b] == oracle.expectation(n, psi, C) == hist[T]
-        oi, op, ke = oracle.topk(n, psi, k)
+        oi, op, ke = oracle.topk(n, psi, k, free=oracle.free_mask(n, u, v, w))
         assert np.array_equal(idx[b], oi) and np.array_equal(prob[b], op)
     # the edgeless subgraph never moves (its gradient is exactly 0)
     assert np.array_equal(gf[4], g0[4]) and np.array_equal(bf[4], b0[4]) and E[4] == 0.0
