@@ -16,7 +16,7 @@ The same line carries the learned-warm-start solve of the same graph: the
 angle predictor (committed weights, trained on plain-method runs of other
 seeds) gives every subgraph its starting angles on the device, each subgraph
 falls back to the plain method's cold start where that start has the larger
-<C>, then 10 Adam steps and the same finish. Both solve times (pipelined, and
+<C>, then 5 Adam steps (step size 0.02) and the same finish. Both solve times (pipelined, and
 the latency of one solve run alone with its merge in line) and both merged cuts
 are reported.
 
@@ -147,7 +147,8 @@ def workload_solve(args, name):
         skip = True
         desc = "2k-vertex solve: G(2000,0.01) seed 0, ragged chain of 14..26-qubit subgraphs, edgeless " \
                "skipped, p=3, top-16, beam 4096, CutVal; plain = cold start + 50 Adam steps, learned = " \
-               f"predicted start (cold-start fallback per subgraph) + {args.warm_iters} Adam steps"
+               f"predicted start (cold-start fallback per subgraph) + {args.warm_iters} Adam steps at step size " \
+               f"{args.warm_lr}"
     cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
     log(f"bench: graph {g}, {part.M} subgraphs of sizes {min(part.size)}..{max(part.size)}, p={cfg.p}, "
         f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
@@ -173,7 +174,7 @@ def workload_solve(args, name):
 
     def learned_step(ov=overlap):
         S.rebuild()
-        S.run_learned(LS, args.warm_iters, overlap=ov)
+        S.run_learned(LS, args.warm_iters, overlap=ov, lr=args.warm_lr)
 
     def plain_alone():
         S.rebuild()
@@ -191,16 +192,19 @@ def workload_solve(args, name):
         timed the same way, and the latency of one solve of each kind."""
         if LS is None:
             return {}
-        out = {"plain": dict(result(), seconds=round(plain_s, 4), adam_steps=cfg.iters)}
+        out = {"plain": dict(result(), seconds=round(plain_s, 4), adam_steps=cfg.iters, adam_lr=cfg.lr)}
         log(f"bench: learned-warm-start solves ({args.warm_iters} Adam steps), {args.steps} timed")
         learned_step()
         learned_s = time_solves(learned_step, args.steps)
-        out["learned"] = dict(result(), seconds=round(learned_s, 4), adam_steps=args.warm_iters)
+        out["learned"] = dict(result(), seconds=round(learned_s, 4), adam_steps=args.warm_iters,
+                              adam_lr=args.warm_lr)
         log(f"bench: latency of single solves (merge in line), {args.latency_solves} of each")
         out["plain"]["latency_seconds"] = round(time_solves(plain_alone, args.latency_solves, True), 4)
         out["learned"]["latency_seconds"] = round(time_solves(lambda: learned_step(False), args.latency_solves,
                                                               True), 4)
         out["learned_vs_plain"] = {"speedup": round(plain_s / learned_s, 3),
+                                   "sum_E_ratio": round(out["learned"]["sum_E_with_edges"] /
+                                                        out["plain"]["sum_E_with_edges"], 5),
                                    "latency_speedup": round(out["plain"]["latency_seconds"] /
                                                             out["learned"]["latency_seconds"], 3),
                                    "cut_ratio": round(out["learned"]["cut"] / out["plain"]["cut"], 4)}
@@ -316,7 +320,8 @@ def main():
                     help="mixer precision mode (precision26 only)")
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
     ap.add_argument("--no-learned", action="store_true", help="ragged2000: skip the learned-warm-start solves")
-    ap.add_argument("--warm-iters", type=int, default=10, help="Adam steps of a learned-warm-start solve")
+    ap.add_argument("--warm-iters", type=int, default=5, help="Adam steps of a learned-warm-start solve")
+    ap.add_argument("--warm-lr", type=float, default=0.02, help="Adam step size of a learned-warm-start solve")
     ap.add_argument("--predictor", default=None, help="trained angle predictor (.npz); default: the package's")
     ap.add_argument("--latency-solves", type=int, default=3, help="single solves timed alone, per kind")
     ap.add_argument("--no-cpu-baseline", action="store_true")

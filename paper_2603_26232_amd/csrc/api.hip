@@ -617,6 +617,15 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
                             (long long)e, u, v, n);
         }
     }
+    // free vertices: no edge of positive weight inside the subgraph; the
+    // state is exactly invariant under flipping their bits (top-k ties)
+    for (int b = 0; b < B; ++b) {
+        SubDesc& d = P.subs[b];
+        uint32_t busy = 0;
+        for (int64_t e = edge_offsets[b]; e < edge_offsets[b + 1]; ++e)
+            if (!edge_w || edge_w[e] > 0) busy |= (1u << edge_u[e]) | (1u << edge_v[e]);
+        d.freem = (uint32_t)((1ull << d.n) - 1ull) & ~busy;
+    }
     if (!d_workspace) return fail(QAOA_ERR_INVALID_ARG, "d_workspace is NULL");
     if (((uintptr_t)d_workspace) % 256) return fail(QAOA_ERR_INVALID_ARG, "d_workspace not 256-byte aligned");
     if (workspace_bytes < P.total)

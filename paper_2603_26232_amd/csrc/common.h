@@ -42,6 +42,8 @@ struct SubDesc {
     int32_t nedges;
     int32_t skip;  // edgeless and not simulated (closed form)
     int32_t tabw;  // bytes per cut-table entry: 1 (weight sum <= 255) or 2
+    uint32_t freem;  // vertices without an edge of positive weight (bit j = local vertex j)
+    int32_t pad_;
     uint64_t psi, lam, tab, tabB, lut, coef, edges;  // byte offsets into the workspace
 };
 

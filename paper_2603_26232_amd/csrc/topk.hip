@@ -1,23 +1,113 @@
 // Top-k bitstring extraction (paper Sec. 3.3.2, Selective Distribution
 // Exploration): per subgraph, the k bitstrings with the largest probability
-// pi(z) = |psi(z)|^2, ordered by (pi descending, z ascending).
+// pi(z) = |psi(z)|^2.
 //
-// Each candidate becomes one unique 64-bit key, (bits of pi as float) << 32 |
-// (0xFFFFFFFF - z): pi >= 0, so the float bit pattern orders like the value,
-// and a larger low word means a smaller z. Every valid key is nonzero (z <
-// 2^30), so 0 serves as padding below all of them.
+// Ties. pi(z) is exactly invariant under flipping the bit of a free vertex
+// (one without an edge of positive weight in the subgraph: its qubit stays
+// in |+>) and under the complement. The candidates these moves connect form
+// a tie group: with Fm = the free vertices (other than vertex 0 in canonical
+// mode), a group is {r0 ^ S} or, when the complement move stays inside the
+// candidates (raw mode, or canonical mode with vertex 0 free) and the
+// subgraph has a vertex that is not free, {r0 ^ S} u {r1 ^ S}, S over the
+// subsets of Fm; r0 < r1 have no bit in Fm and are each other's complement
+// (with bit 0 flipped back in canonical mode) restricted to the other bits.
+// The order is the group's probability descending, then r0 ascending, then
+// a fixed bijective rank of the string inside the group; in FP32, members of
+// one group would otherwise be ordered by rounding noise. So stage 1 keeps
+// only the representatives r0, and stage 2 expands each selected group into
+// its members in rank order: member j of a group of 2^m is the index
+// x = rank^-1(j) (half in the low bit when there are two halves, the bits of
+// S at Fm above it), rank(x) = g(A g(x) mod 2^m), g(x) = x ^ (x >> ceil(m/2))
+// (a xorshift step, its own inverse on m bits) and A = 2654435761 (Knuth's
+// multiplicative hashing); rank^-1(j) = g(A^-1 g(j) mod 2^m).
+//
+// Each representative becomes one unique 64-bit key, (bits of pi as float)
+// << 32 | (0xFFFFFFFF - z): pi >= 0, so the float bit pattern orders like
+// the value, and a larger low word means a smaller z. Every valid key is
+// nonzero (z < 2^30), so 0 serves as padding below all of them.
 //
 // Both stages find the k largest keys of a set by a most-significant-digit
 // radix select in LDS (8-bit digits, one histogram per digit, stopping as
 // soon as every key that shares the current prefix is needed), instead of
 // sorting: stage 1 takes one 4096-amplitude tile of the reduced state per
 // block, with its candidates in registers, and writes the tile's best k
-// unsorted; stage 2 selects a subgraph's best k from its per-tile lists and
-// sorts only those.
+// unsorted; stage 2 selects a subgraph's best k from its per-tile lists,
+// sorts only those and expands them.
 // Canonical mode takes only z with bit 0 clear (pi(z) = pi(~z)).
 #include "common.h"
 
 namespace pq {
+
+// tie groups of one subgraph (see the file comment)
+struct TieGroups {
+    uint32_t fm;    // free vertices that a group's strings may differ in
+    uint32_t full;  // all n bits
+    int halves;     // 2: a group also holds the complement-side half
+    int m;          // a group has 2^m strings
+    int canonical;
+};
+
+__device__ inline TieGroups tie_groups(const SubDesc* d, int canonical)
+{
+    TieGroups t;
+    t.full = (uint32_t)((1ull << d->n) - 1ull);
+    t.fm = canonical ? (d->freem & ~1u) : d->freem;
+    const bool part_ok = canonical ? (d->freem & 1u) != 0u : true;
+    t.halves = (part_ok && d->freem != t.full) ? 2 : 1;
+    t.m = __popc(t.fm) + (t.halves == 2 ? 1 : 0);
+    t.canonical = canonical;
+    return t;
+}
+
+// the complement move restricted to the bits outside Fm
+__device__ inline uint32_t partner_base(const TieGroups& t, uint32_t z)
+{
+    const uint32_t c = (~z & t.full) ^ (t.canonical ? 1u : 0u);
+    return c & ~t.fm;
+}
+
+// is z the representative (smallest base) of its tie group?
+__device__ inline bool is_representative(const TieGroups& t, uint32_t z)
+{
+    if (z & t.fm) return false;
+    return t.halves == 1 || z <= partner_base(t, z);
+}
+
+constexpr uint32_t TIE_MUL_INV = 0x0E8B2F51u;  // 2654435761^-1 mod 2^32
+static_assert(2654435761u * TIE_MUL_INV == 1u, "multiplicative inverse");
+
+__device__ inline uint32_t tie_unrank(uint32_t j, int m)
+{
+    if (m <= 0) return 0u;
+    const uint32_t mask = m >= 32 ? 0xFFFFFFFFu : ((1u << m) - 1u);
+    const int s = (m + 1) / 2;
+    uint32_t x = j ^ (j >> s);
+    x = (x * TIE_MUL_INV) & mask;  // mod 2^32 then mod 2^m
+    return x ^ (x >> s);
+}
+
+// deposit the low bits of v at the set positions of mask
+__device__ inline uint32_t deposit_bits(uint32_t v, uint32_t mask)
+{
+    uint32_t out = 0;
+    for (int j = 0; j < 32 && mask; ++j) {
+        const uint32_t low = mask & (0u - mask);
+        if (v & 1u) out |= low;
+        v >>= 1;
+        mask ^= low;
+    }
+    return out;
+}
+
+// string j (in rank order) of the group with representative r0
+__device__ inline uint32_t tie_member(const TieGroups& t, uint32_t r0, uint32_t j)
+{
+    const uint32_t x = tie_unrank(j, t.m);
+    const uint32_t half = t.halves == 2 ? (x & 1u) : 0u;
+    const uint32_t sp = t.halves == 2 ? (x >> 1) : x;
+    const uint32_t base = half ? partner_base(t, r0) : r0;
+    return base ^ deposit_bits(sp, t.fm);
+}
 
 struct SelState {
     int hist[256];
@@ -115,6 +205,7 @@ __global__ __launch_bounds__(THREADS) void k_topk_tile(const uint8_t* ws, const 
     const float2* st = (const float2*)(ws + d->psi) + base;
     const uint32_t span = n - 1 < TILE_BITS ? (1u << (n - 1)) : (uint32_t)TILE;
     const uint32_t full = (uint32_t)((1ull << n) - 1ull);
+    const TieGroups tg = tie_groups(d, CANON ? 1 : 0);
     const int t = threadIdx.x;
     uint64_t key[PER];
 #pragma unroll
@@ -125,11 +216,13 @@ __global__ __launch_bounds__(THREADS) void k_topk_tile(const uint8_t* ws, const 
         if (ok) a = st[c];
         const float pr = 0.5f * (a.x * a.x + a.y * a.y);
         const uint32_t z = base + c;
+        // only the representatives of tie groups are ranked
         if (CANON) {
-            key[j] = ok ? make_key(pr, (z & 1u) ? z ^ full : z) : 0ull;
+            const uint32_t zc = (z & 1u) ? z ^ full : z;
+            key[j] = (ok && is_representative(tg, zc)) ? make_key(pr, zc) : 0ull;
         } else {
-            key[2 * j] = ok ? make_key(pr, z) : 0ull;
-            key[2 * j + 1] = ok ? make_key(pr, z ^ full) : 0ull;
+            key[2 * j] = (ok && is_representative(tg, z)) ? make_key(pr, z) : 0ull;
+            key[2 * j + 1] = (ok && is_representative(tg, z ^ full)) ? make_key(pr, z ^ full) : 0ull;
         }
     }
     const int cnt = (int)(CANON ? span : 2 * span);
@@ -160,14 +253,17 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_topk_merge(const SubDesc* sub
     const int b = blockIdx.x;
     const SubDesc* d = subs + b;
     const int t = threadIdx.x;
+    const TieGroups tg = tie_groups(d, canonical);
     if (d->skip) {
-        // edgeless subgraph: |psi|^2 = 2^-n everywhere, ties broken by index
-        const uint32_t step = canonical ? 2u : 1u;
-        const uint64_t cnt = (1ull << d->n) / step;
-        for (int i = t; i < k; i += MERGE_THREADS) {
-            const bool ok = (uint64_t)i < cnt;
-            idx[(size_t)b * k + i] = ok ? (uint32_t)i * step : 0xFFFFFFFFu;
-            prob[(size_t)b * k + i] = ok ? ldexpf(1.0f, -d->n) : -1.0f;
+        // edgeless subgraph: |psi|^2 = 2^-n everywhere, so all candidates form
+        // one tie group (every vertex free) with representative 0
+        if (t == 0) {
+            const uint64_t group = 1ull << tg.m;
+            for (int i = 0; i < k; ++i) {
+                const bool ok = (uint64_t)i < group;
+                idx[(size_t)b * k + i] = ok ? tie_member(tg, 0u, (uint32_t)i) : 0xFFFFFFFFu;
+                prob[(size_t)b * k + i] = ok ? ldexpf(1.0f, -d->n) : -1.0f;
+            }
         }
         return;
     }
@@ -203,14 +299,23 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_topk_merge(const SubDesc* sub
             __syncthreads();
         }
     }
-    for (int i = t; i < k; i += MERGE_THREADS) {
-        const uint64_t key = S.out[i];
-        if (key == 0ull) {
-            idx[(size_t)b * k + i] = 0xFFFFFFFFu;
-            prob[(size_t)b * k + i] = -1.0f;
-        } else {
-            idx[(size_t)b * k + i] = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
-            prob[(size_t)b * k + i] = __uint_as_float((uint32_t)(key >> 32));
+    // expand the selected groups, in order, into their strings in rank order
+    if (t == 0) {
+        const uint64_t group = 1ull << tg.m;
+        int out = 0;
+        for (int i = 0; i < k && out < k; ++i) {
+            const uint64_t key = S.out[i];
+            if (key == 0ull) break;
+            const uint32_t r0 = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull);
+            const float pr = __uint_as_float((uint32_t)(key >> 32));
+            for (uint64_t j = 0; j < group && out < k; ++j, ++out) {
+                idx[(size_t)b * k + out] = tie_member(tg, r0, (uint32_t)j);
+                prob[(size_t)b * k + out] = pr;
+            }
+        }
+        for (; out < k; ++out) {
+            idx[(size_t)b * k + out] = 0xFFFFFFFFu;
+            prob[(size_t)b * k + out] = -1.0f;
         }
     }
 }

@@ -23,6 +23,10 @@ class SolveConfig:
     k: int = 16                # top-k per subgraph
     beam: int = 4096           # merge beam width W
     lr: float = 0.05
+    # Adam step size of learned-warm-start solves: their start is close to an
+    # optimum, where steps of 0.05 (the size of Adam's first bias-corrected
+    # steps) overshoot; 0.02 was chosen on the predictor's training graphs
+    warm_lr: float = 0.02
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
@@ -122,12 +126,13 @@ class Solver:
         self.v.zero_()
         self.step.zero_()
 
-    def optimise(self, iters: int, stream=None):
+    def optimise(self, iters: int, stream=None, lr=None):
         """`iters` Adam ascent steps on every subgraph's <C>, one library call
-        (no host sync)."""
+        (no host sync); lr defaults to the configuration's."""
         cfg = self.cfg
         _abi.qaoa_optimize(self.batch.handle, cfg.p, iters, _ptr(self.theta), _ptr(self.m), _ptr(self.v),
-                           _ptr(self.step), cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, _ptr(self.E), _stream(stream))
+                           _ptr(self.step), cfg.lr if lr is None else lr, cfg.beta1, cfg.beta2, cfg.eps,
+                           _ptr(self.E), _stream(stream))
 
     def optimise_separate(self, iters: int, stream=None):
         """The same steps as separate gradient and Adam calls (reference for
@@ -222,14 +227,15 @@ class Solver:
             self.optimise(n, stream)
         self.finish(stream, overlap=overlap)
 
-    def run_learned(self, start, iters: int, stream=None, overlap=False):
+    def run_learned(self, start, iters: int, stream=None, overlap=False, lr=None):
         """A learned-warm-start solve: `start` (a learned.LearnedStart of this
         solver) enqueues the predicted angles, with each subgraph falling back
         to the cold start where that start's <C> is larger; then `iters` Adam
-        steps and the same finish as the plain method (device only)."""
+        steps (step size lr, default the configuration's warm_lr) and the same finish
+        as the plain method (device only)."""
         start.start(stream)
         if iters > 0:
-            self.optimise(iters, stream)
+            self.optimise(iters, stream, lr=self.cfg.warm_lr if lr is None else lr)
         self.finish(stream, overlap=overlap)
 
     def result(self) -> SolveResult:

@@ -33,7 +33,7 @@ from .batch import _ptr, _stream
 from . import _abi
 
 
-def run_with_history(S: Solver, gamma0, beta0, iters: int, start=None):
+def run_with_history(S: Solver, gamma0, beta0, iters: int, start=None, lr=None):
     """Adam steps from the given angles (or from a learned.LearnedStart's
     start, with its per-subgraph cold-start fallback); returns E at the start
     of every step and after the last ([iters + 1, B] numpy) and leaves the
@@ -50,8 +50,8 @@ def run_with_history(S: Solver, gamma0, beta0, iters: int, start=None):
     for t in range(iters):
         _abi.qaoa_expectation_grad(S.batch.handle, cfg.p, th, th + 8 * P, _ptr(S.E), gr, gr + 8 * P, s)
         hist[t].copy_(S.E)
-        _abi.qaoa_adam_step(2 * P, th, gr, _ptr(S.m), _ptr(S.v), _ptr(S.step), cfg.lr, cfg.beta1, cfg.beta2,
-                            cfg.eps, 1, s)
+        _abi.qaoa_adam_step(2 * P, th, gr, _ptr(S.m), _ptr(S.v), _ptr(S.step), cfg.lr if lr is None else lr,
+                            cfg.beta1, cfg.beta2, cfg.eps, 1, s)
     _abi.qaoa_apply_layers(S.batch.handle, cfg.p, th, th + 8 * P, s)
     _abi.qaoa_expectation(S.batch.handle, _ptr(S.E), s)
     hist[iters].copy_(S.E)
@@ -126,7 +126,7 @@ def compare(model: AnglePredictor, g, part, p=3, T_max=200, plain_iters=50, warm
     # warm start: predicted angles on the device, each subgraph falling back
     # to the cold start where that start's <C> is larger
     LS = LearnedStart(S, model)
-    hist_warm = run_with_history(S, None, None, T_max, start=LS)
+    hist_warm = run_with_history(S, None, None, T_max, start=LS, lr=cfg.warm_lr)
     it_warm = iterations_to_converge(hist_warm, E_star, nE)
     out = {"subgraphs": int(S.B), "with_edges": int(act.sum()), "T_max": T_max,
            "plain_iters": plain_iters, "plain_cut": r_plain.cut, "plain_solve_s": t_plain,

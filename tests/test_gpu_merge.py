@@ -200,7 +200,7 @@ def test_plain_solve_400_vertices_full_size():
         assert np.max(np.abs(st - psi)) <= 1e-5
         e_ref = oracle.expectation(20, psi, C)
         assert abs(r.energies[b] - e_ref) <= 1e-5 * max(1.0, e_ref)
-        _accept_topk(r.cand[b], S.prob.view(part.M, -1)[b].cpu().numpy(), psi, cfg.k)
+        _accept_topk(r.cand[b], S.prob.view(part.M, -1)[b].cpu().numpy(), psi, cfg.k, free=oracle.free_mask(20, u, v, w))
     ref_cut, ref_x, _, _ = oracle.merge(400, part.start, part.size, g.u, g.v, g.w, r.cand, W=cfg.beam)
     assert r.cut == ref_cut and np.array_equal(r.assignment, ref_x)
     S.close()

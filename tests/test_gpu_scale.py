@@ -130,15 +130,20 @@ def test_ragged2000_solve_end_to_end(tuned_splits):
             print(f"  final state b={b} n={part.size[b]}", flush=True)
             assert np.max(np.abs(got[b] - psi)) <= AMP_TOL
             assert abs(r.energies[b] - e_ref) <= E_TOL * max(1.0, e_ref)
-            _accept_topk(r.cand[b], probs[b], psi, cfg.k)
+            u, v, w = S.sub_edges[b]
+            _accept_topk(r.cand[b], probs[b], psi, cfg.k, free=oracle.free_mask(int(part.size[b]), u, v, w))
     # 104-level merge of the GPU's candidates and CutVal, bit-exact
     ref_cut, ref_x, _, _ = oracle.merge(2000, part.start, part.size, g.u, g.v, g.w, r.cand, W=cfg.beam)
     print(f"  merge: {part.M} levels, cut {r.cut} (oracle {ref_cut})", flush=True)
     assert r.cut == ref_cut and np.array_equal(r.assignment, ref_x)
     assert oracle.cutval(g.u, g.v, g.w, r.assignment) == r.cut
-    # edgeless subgraphs are closed-form: <C> = 0, top-16 = the 16 smallest canonical indices
+    # edgeless subgraphs are closed-form: <C> = 0, top-16 = the first 16
+    # strings of their single tie group in the oracle's rank order
     for b in np.nonzero(nE == 0)[0][:5]:
-        assert r.energies[b] == 0.0 and list(r.cand[b]) == list(range(0, 32, 2))
+        n = int(part.size[b])
+        uniform = np.full(1 << n, 2.0 ** (-n / 2), dtype=np.complex128)
+        oi, _, _ = oracle.topk(n, uniform, cfg.k, True, (1 << n) - 1)
+        assert r.energies[b] == 0.0 and np.array_equal(r.cand[b], oi)
     S.close()
 
 

@@ -150,17 +150,44 @@ def test_determinism():
     bt.close()
 
 
-def _accept_topk(got_idx, got_prob, psi, k, canonical=True, eps=1e-5):
+def _tie_group(z, n, free, canonical):
+    """(representative, index inside the group, m) of z's tie group, as the
+    oracle's top-k defines them (free vertices and the complement move)."""
+    full = (1 << n) - 1
+    fm = free & ~1 if canonical else free
+    halves = 2 if ((free & 1 if canonical else 1) and free != full) else 1
+    m = bin(fm).count("1") + (1 if halves == 2 else 0)
+    rep, half = z & ~fm, 0
+    if halves == 2:
+        r2 = (((~z) & full) ^ (1 if canonical else 0)) & ~fm
+        if r2 < rep:
+            rep, half = r2, 1
+    x, t = 0, 0
+    for j in range(n):
+        if fm >> j & 1:
+            x |= ((z >> j) & 1) << t
+            t += 1
+    return rep, ((x << 1) | half) if halves == 2 else x, m
+
+
+def _accept_topk(got_idx, got_prob, psi, k, canonical=True, free=0, eps=1e-5):
     """Tolerance-aware acceptance of a GPU top-k list against the FP64 state:
     distinct (canonical) indices, every pick within 2*delta of the oracle's
-    k-th probability, adjacent pairs in oracle order unless within 2*delta."""
+    k-th probability, adjacent pairs in oracle order unless within 2*delta;
+    each tie group (free-vertex mask `free`) appears as one contiguous block
+    of its strings in the oracle's rank order 0, 1, 2, ...; and when no two
+    different groups come within 2*delta of each other at the list's
+    boundaries, the list equals the oracle's."""
     n_amp = psi.shape[0]
+    n = n_amp.bit_length() - 1
     pr = np.abs(psi) ** 2
     delta = eps * (2 * np.abs(psi).max() + eps)
-    cand = np.arange(0, n_amp, 2 if canonical else 1)
-    k_eff = min(k, cand.shape[0])
-    order = cand[np.lexsort((cand, -pr[cand]))]
-    kth = pr[order[k_eff - 1]]
+    n_cand = n_amp // 2 if canonical else n_amp
+    k_eff = min(k, n_cand)
+    k2 = min(n_cand, k + 64)
+    oi, op, _ = oracle.topk(n, psi, k2, canonical, free)
+    oi = oi.astype(np.int64)
+    kth = pr[oi[k_eff - 1]]
     gi = got_idx[:k_eff].astype(np.int64)
     assert np.all(got_idx[k_eff:] == 0xFFFFFFFF) and np.all(got_prob[k_eff:] == -1.0)
     assert len(set(gi.tolist())) == k_eff
@@ -170,16 +197,40 @@ def _accept_topk(got_idx, got_prob, psi, k, canonical=True, eps=1e-5):
     for a, b in zip(gi[:-1], gi[1:]):
         assert pr[a] > pr[b] - 2 * delta or (abs(pr[a] - pr[b]) <= 2 * delta)
     assert np.all(np.abs(got_prob[:k_eff] - pr[gi]) <= 2 * delta)
-    # when every gap is clear the lists are identical
-    gaps = np.abs(np.diff(pr[order[:k_eff + 1]])) if k_eff < cand.shape[0] else np.abs(np.diff(pr[order[:k_eff]]))
+    # groups: contiguous blocks in rank order
+    seen, cur, nxt = set(), None, 0
+    for z in gi.tolist():
+        rep, x, m = _tie_group(z, n, free, canonical)
+        if rep != cur:
+            assert rep not in seen, "a tie group appears in two blocks"
+            seen.add(rep)
+            cur, nxt = rep, 0
+        assert oracle.tie_rank(x, m) == nxt, (z, rep, x, m, nxt)
+        nxt += 1
+    # clear boundaries between the groups that fill the list (and the next
+    # one): identical lists
+    full = (1 << n) - 1
+    fm = free & ~1 if canonical else free
+    halves = 2 if ((free & 1 if canonical else 1) and free != full) else 1
+    z = np.arange(0, n_amp, 2 if canonical else 1, dtype=np.int64)
+    keep = (z & fm) == 0
+    if halves == 2:
+        keep &= z <= ((((~z) & full) ^ (1 if canonical else 0)) & ~fm)
+    reps = z[keep]
+    reps = reps[np.lexsort((reps, -pr[reps]))]
+    size = 1 << (bin(fm).count("1") + (1 if halves == 2 else 0))
+    need = min(len(reps), -(-k_eff // size) + 1)
+    gaps = np.abs(np.diff(pr[reps[:need]]))
     if gaps.size == 0 or gaps.min() > 2 * delta:
-        assert np.array_equal(gi, order[:k_eff])
+        assert np.array_equal(gi, oi[:k_eff])
 
 
-@pytest.mark.parametrize("sizes,k,raw", [([12], 8, False), ([3, 5, 13, 20], 16, False),
-                                         ([14, 21], 16, True), ([2, 4], 64, False)])
-def test_topk(sizes, k, raw):
-    edges = _subgraphs(sizes, 40 + k)
+@pytest.mark.parametrize("sizes,k,raw,p_edge", [([12], 8, False, 0.4), ([3, 5, 13, 20], 16, False, 0.4),
+                                                ([14, 21], 16, True, 0.4), ([2, 4], 64, False, 0.4),
+                                                ([14, 21, 9, 17], 16, False, 0.08), ([15, 20, 6], 40, True, 0.06)])
+def test_topk(sizes, k, raw, p_edge):
+    """Sparse cases have free vertices: their strings come in tie groups."""
+    edges = _subgraphs(sizes, 40 + k, p_edge=p_edge)
     p = 3
     gamma, beta = synth.uniform_angles(500 + k, p, batch=len(sizes))
     bt = QaoaBatch(sizes, edges, max_p=p, max_k=k, raw_topk=raw)
@@ -191,7 +242,7 @@ def test_topk(sizes, k, raw):
         u, v, w = edges[b]
         C = oracle.cut_table(n, u, v, w)
         psi = oracle.qaoa_state(n, C, gamma[b], beta[b])
-        _accept_topk(gi[b], gp[b], psi, k, canonical=not raw)
+        _accept_topk(gi[b], gp[b], psi, k, canonical=not raw, free=oracle.free_mask(n, u, v, w))
     bt.close()
 
 
@@ -253,15 +304,17 @@ def test_skip_edgeless_matches_simulation():
     (E0, i0, p0, Eg0, dg0, db0), (E1, i1, p1, Eg1, dg1, db1) = out
     assert np.array_equal(E0, E1) and np.array_equal(Eg0, Eg1)
     assert np.array_equal(dg0, dg1) and np.array_equal(db0, db1)
-    # subgraphs with edges: identical; edgeless ones: the simulated
-    # probabilities tie up to FP32 rounding (any order is acceptable), the
-    # closed form breaks the exact tie by index
+    # subgraphs with edges: identical; edgeless ones: every vertex is free,
+    # so simulated and closed form list the one tie group in the same rank
+    # order (the oracle's, on the uniform state), with probability 2^-n
     for b in (0, 3):
         assert np.array_equal(i0[b], i1[b]) and np.array_equal(p0[b], p1[b])
     for b, n in ((1, 9), (2, 20)):
-        assert list(i1[b]) == [0, 2, 4, 6, 8, 10, 12, 14]
+        uniform = np.full(1 << n, 2.0 ** (-n / 2), dtype=np.complex128)
+        oi, _, _ = oracle.topk(n, uniform, 8, True, (1 << n) - 1)
+        assert np.array_equal(i1[b], oi) and np.array_equal(i0[b], oi)
         assert np.all(p1[b] == np.float32(2.0 ** -n))
-        assert np.allclose(p0[b], 2.0 ** -n, rtol=1e-5, atol=0) and np.all(i0[b] % 2 == 0)
+        assert np.allclose(p0[b], 2.0 ** -n, rtol=1e-5, atol=0)
     ref.close()
     skp.close()
 
