@@ -112,9 +112,20 @@ __device__ inline uint32_t tie_member(const TieGroups& t, uint32_t r0, uint32_t 
 struct SelState {
     int hist[256];
     int wsum[16];
-    int digit, qrem, done, count;
+    int digit, qrem, done, count, nonzero;
     uint64_t out[MAX_K];
 };
+
+// number of nonzero keys over the block (each thread passes its own count)
+__device__ inline int count_nonzero(SelState& S, int mine)
+{
+    if (threadIdx.x == 0) S.nonzero = 0;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+    if ((threadIdx.x & 63u) == 0 && mine) atomicAdd(&S.nonzero, mine);
+    __syncthreads();
+    return S.nonzero;
+}
 
 // the digit (from the top) that holds the q-th largest counted key; sets
 // done when exactly q keys were counted (then all of them are taken)
@@ -149,9 +160,10 @@ __device__ void pick_digit(SelState& S, int q)
 }
 
 // Radix select of the q largest keys produced by src(i), i < n_local per
-// thread. Returns (prefix, digits) such that a key is among the q largest iff
-// digits == 0 or key >> (64 - 8 digits) >= prefix. With unique keys this
-// selects exactly q; with repeated keys (padding) it may select more.
+// thread. Returns (prefix, digits) such that a nonzero key is among the q
+// largest iff digits == 0 or key >> (64 - 8 digits) >= prefix. Zero keys
+// (padding) are not counted, so q must not exceed the number of nonzero
+// keys (otherwise no digit is found); with unique keys this selects exactly q.
 template <typename Src>
 __device__ void radix_select(SelState& S, const Src& src, int n_local, int q, uint64_t& prefix, int& digits)
 {
@@ -164,7 +176,8 @@ __device__ void radix_select(SelState& S, const Src& src, int n_local, int q, ui
         const int shift = 56 - 8 * r;
         for (int i = 0; i < n_local; ++i) {
             const uint64_t key = src(i);
-            if (r == 0 || (key >> (shift + 8)) == prefix) atomicAdd(&S.hist[(int)((key >> shift) & 255)], 1);
+            if (key != 0ull && (r == 0 || (key >> (shift + 8)) == prefix))
+                atomicAdd(&S.hist[(int)((key >> shift) & 255)], 1);
         }
         __syncthreads();
         pick_digit(S, q);
@@ -225,12 +238,15 @@ __global__ __launch_bounds__(THREADS) void k_topk_tile(const uint8_t* ws, const 
             key[2 * j + 1] = (ok && is_representative(tg, z ^ full)) ? make_key(pr, z ^ full) : 0ull;
         }
     }
-    const int cnt = (int)(CANON ? span : 2 * span);
+    int mine = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) mine += key[i] != 0ull;
+    const int cnt = count_nonzero(S, mine);  // the tile's representatives
     const int q = k < cnt ? k : cnt;
-    uint64_t prefix;
-    int digits;
+    uint64_t prefix = 0;
+    int digits = 0;
     if (t == 0) S.count = 0;
-    radix_select(S, [&](int i) { return key[i]; }, PER, q, prefix, digits);
+    if (q > 0) radix_select(S, [&](int i) { return key[i]; }, PER, q, prefix, digits);
     uint64_t* o = out + ((size_t)d->tile_base + wk.y) * k;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
@@ -270,11 +286,15 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_topk_merge(const SubDesc* sub
     const int total = d->ntiles * k;
     const uint64_t* src = in + (size_t)d->tile_base * k;
     const int nloc = (total - t + MERGE_THREADS - 1) / MERGE_THREADS;  // keys t, t + 1024, ...
-    uint64_t prefix;
-    int digits;
+    uint64_t prefix = 0;
+    int digits = 0;
+    int mine = 0;
+    for (int i = 0; i < nloc; ++i) mine += src[t + (size_t)i * MERGE_THREADS] != 0ull;
+    const int cnt = count_nonzero(S, mine);
+    const int q = k < cnt ? k : cnt;
     if (t == 0) S.count = 0;
     if (t < MAX_K) S.out[t] = 0ull;
-    radix_select(S, [&](int i) { return src[t + (size_t)i * MERGE_THREADS]; }, nloc, k, prefix, digits);
+    if (q > 0) radix_select(S, [&](int i) { return src[t + (size_t)i * MERGE_THREADS]; }, nloc, q, prefix, digits);
     for (int i = 0; i < nloc; ++i) {
         const uint64_t key = src[t + (size_t)i * MERGE_THREADS];
         if (key != 0ull && selected(key, prefix, digits)) {
