@@ -131,6 +131,7 @@ def workload_solve(args, name):
     """plain400 / ragged2000: the plain-method solve as one step; ragged2000
     also times the learned-warm-start solve of the same graph."""
     import numpy as np
+    import torch
     from paper_2603_26232_amd import synth
     from paper_2603_26232_amd.partition import partition_equal, partition_chain
     from paper_2603_26232_amd.solve import Solver, SolveConfig, cold_start
@@ -170,7 +171,7 @@ def workload_solve(args, name):
 
     def step():
         S.rebuild()
-        S.run(graph=args.graph, overlap=overlap)
+        S.run(overlap=overlap)
 
     def learned_step(ov=overlap):
         S.rebuild()
@@ -178,7 +179,11 @@ def workload_solve(args, name):
 
     def plain_alone():
         S.rebuild()
-        S.run(graph=args.graph, overlap=False)
+        S.run(overlap=False)
+
+    def graph_step():
+        S.rebuild()
+        S.run(graph=True, overlap=overlap)
 
     def result():
         r = S.result()
@@ -187,12 +192,29 @@ def workload_solve(args, name):
     def summary():
         return {"solve": result()}
 
+    def graph_compare(plain_s, ref):
+        """The same plain solves with the 50 Adam steps replayed from one
+        captured HIP graph (captured by the first, untimed solve)."""
+        log(f"bench: plain solves with the {cfg.iters}-step Adam loop in one HIP graph, {args.steps} timed")
+        c0 = time.perf_counter()
+        graph_step()
+        torch.cuda.synchronize()
+        first = time.perf_counter() - c0
+        gs = time_solves(graph_step, args.steps)
+        r = result()
+        log(f"bench: graph replay {gs:.4f} s/solve (eager {plain_s:.4f}), first solve with capture {first:.2f} s")
+        return {"seconds": round(gs, 4), "eager_seconds": round(plain_s, 4), "speedup_vs_eager": round(plain_s / gs, 4),
+                "first_solve_with_capture_seconds": round(first, 3), "same_result_as_eager": r == ref}
+
     def extra(plain_s):
-        """After the timed plain solves: their result, the learned solves
-        timed the same way, and the latency of one solve of each kind."""
-        if LS is None:
-            return {}
+        """After the timed plain solves: their result, the plain solves with
+        the Adam loop replayed from a HIP graph, the learned solves timed the
+        same way, and the latency of one solve of each kind."""
         out = {"plain": dict(result(), seconds=round(plain_s, 4), adam_steps=cfg.iters, adam_lr=cfg.lr)}
+        if not args.no_graph_compare:
+            out["plain_graph_replay"] = graph_compare(plain_s, result())
+        if LS is None:
+            return {"solve": out}
         log(f"bench: learned-warm-start solves ({args.warm_iters} Adam steps), {args.steps} timed")
         learned_step()
         learned_s = time_solves(learned_step, args.steps)
@@ -251,7 +273,7 @@ def workload_solve(args, name):
                                "sample": f"every 4th subgraph of that sample ({len(one)}), {T1} Adam steps + "
                                          f"final evaluation"}}
 
-    config = {"workload": desc, "graph_replay": bool(args.graph), "merge_overlaps_next_solve": overlap,
+    config = {"workload": desc, "merge_overlaps_next_solve": overlap,
               "gradient_memory": ("forward checkpoints" if ckpt else "in place") + f" ({args.gradient_memory})",
               "vertices": g.num_vertices, "edges": g.num_edges,
               "subgraphs": part.M, "simulated_subgraphs": len(sim),
@@ -325,7 +347,8 @@ def main():
     ap.add_argument("--predictor", default=None, help="trained angle predictor (.npz); default: the package's")
     ap.add_argument("--latency-solves", type=int, default=3, help="single solves timed alone, per kind")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay the Adam step from a captured HIP graph")
+    ap.add_argument("--no-graph-compare", action="store_true",
+                    help="solve workloads: skip the plain solves with the Adam loop replayed from a HIP graph")
     ap.add_argument("--gradient-memory", choices=["auto", "checkpoints", "inplace"], default="auto",
                     help="forward checkpoints, one psi rebuilt in place, or the library's choice by size")
     ap.add_argument("--tuning", default="default",
@@ -397,8 +420,6 @@ def main():
         _abi.qaoa_profile_enable(0)
     # without a warm-up the last timed step times every kernel instead
     dom = max(kern, key=lambda k: kern[k]["total_ms"]) if kern else None
-    if args.graph:
-        log("bench: Adam steps replay a captured HIP graph")
     log(f"bench: {args.warmup} warmup steps done; timing {args.steps} steps (kernel events on "
         f"{dom or 'every kernel'} in the last)")
     # timed region: events only around the dominant kernel's launches, and

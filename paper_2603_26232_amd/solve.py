@@ -146,28 +146,38 @@ class Solver:
             _abi.qaoa_adam_step(2 * P, th, gr, _ptr(self.m), _ptr(self.v), _ptr(self.step), cfg.lr, cfg.beta1,
                                 cfg.beta2, cfg.eps, 1, s)
 
-    def _one_step(self, s: int):
+    def _steps(self, n: int, s: int):
         cfg = self.cfg
-        _abi.qaoa_optimize(self.batch.handle, cfg.p, 1, _ptr(self.theta), _ptr(self.m), _ptr(self.v),
+        _abi.qaoa_optimize(self.batch.handle, cfg.p, n, _ptr(self.theta), _ptr(self.m), _ptr(self.v),
                            _ptr(self.step), cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, _ptr(self.E), s)
 
-    def optimise_graph(self, iters: int):
-        """Same as `optimise`, replaying one captured HIP graph of an Adam step
-        (angle tables, gradient passes, fused reduction + Adam); the step
-        counter lives on the device, so every replay is the next step. The graph is captured on first use and
-        kept with the solver (it holds this batch's buffers)."""
-        # the captured kernels reference only the workspace (whose layout a
-        # rebuild of the same batch reproduces) and this solver's buffers
-        if getattr(self, "_graph", None) is None:
-            cap = torch.cuda.Stream()
-            cap.wait_stream(torch.cuda.current_stream())
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=cap):
-                self._one_step(int(cap.cuda_stream))
-            torch.cuda.current_stream().wait_stream(cap)
-            self._graph = g
-        for _ in range(iters):
-            self._graph.replay()
+    def optimise_graph(self, iters: int, chunk: int = None):
+        """Same as `optimise`, replaying captured HIP graphs of `chunk` Adam
+        steps each (default: all `iters` steps in one graph; every step is the
+        angle tables, the gradient passes and the fused reduction + Adam). The
+        step counter lives on the device, so each replay continues where the
+        last one stopped. A graph is captured on first use of its step count
+        and kept with the solver (it holds this batch's buffers)."""
+        chunk = iters if chunk is None else max(1, min(chunk, iters))
+        if getattr(self, "_graphs", None) is None:
+            self._graphs = {}
+        done = 0
+        while done < iters:
+            n = min(chunk, iters - done)
+            g = self._graphs.get(n)
+            if g is None:
+                # the captured kernels reference only the workspace (whose
+                # layout a rebuild of the same batch reproduces) and this
+                # solver's buffers
+                cap = torch.cuda.Stream()
+                cap.wait_stream(torch.cuda.current_stream())
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=cap):
+                    self._steps(n, int(cap.cuda_stream))
+                torch.cuda.current_stream().wait_stream(cap)
+                self._graphs[n] = g
+            g.replay()
+            done += n
 
     def _merge_slot(self, k):
         """Buffers of merge slot k: (idx, prob, merge_ws, best, best_cut, eval_cut)."""
@@ -216,13 +226,13 @@ class Solver:
             self._next_slot ^= 1
         self._last_slot = k
 
-    def run(self, gamma0=None, beta0=None, iters=None, stream=None, graph=False, overlap=False):
+    def run(self, gamma0=None, beta0=None, iters=None, stream=None, graph=False, overlap=False, graph_chunk=None):
         if gamma0 is None:
             gamma0, beta0 = cold_start(self.cfg.p, self.B)
         self.set_angles(gamma0, beta0)
         n = self.cfg.iters if iters is None else iters
         if graph:
-            self.optimise_graph(n)
+            self.optimise_graph(n, graph_chunk)
         else:
             self.optimise(n, stream)
         self.finish(stream, overlap=overlap)
@@ -254,6 +264,7 @@ class Solver:
                            cand=idx.cpu().numpy().view(np.uint32).reshape(self.B, -1))
 
     def close(self):
+        self._graphs = None
         self.batch.close()
 
 

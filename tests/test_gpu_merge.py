@@ -230,9 +230,12 @@ def test_fused_optimiser_matches_separate_calls(p_edge, skip):
     S.close()
 
 
-def test_graph_replay_matches_eager_optimiser():
-    """A captured Adam step replayed T times gives bit-identical angles to T
-    eager steps; replays are interleaved with eager work and checked each time."""
+@pytest.mark.parametrize("chunk", [None, 1, 4])
+def test_graph_replay_matches_eager_optimiser(chunk):
+    """Captured Adam steps replayed to T steps give bit-identical angles to T
+    eager steps: the whole loop in one graph (chunk None), one step per graph,
+    and 4-step graphs with a 2-step remainder; replays are interleaved with
+    eager work and checked each time."""
     g = synth.erdos_renyi(90, 0.12, 8)
     part = partition_equal(90, 16)
     cfg = SolveConfig(p=3, iters=6, k=8, beam=64)
@@ -242,11 +245,14 @@ def test_graph_replay_matches_eager_optimiser():
     S.optimise(6)
     torch.cuda.synchronize()
     ref = S.theta.clone()
+    ref_e = S.E.clone()
     for rep in range(3):
         S.set_angles(g0, b0)
-        S.optimise_graph(6)
+        S.optimise_graph(6, chunk)
         torch.cuda.synchronize()
         assert torch.equal(S.theta, ref), rep
+        assert torch.equal(S.E, ref_e), rep
+        assert int(S.step.cpu()[0]) == 6
         # eager work between replays
         S.finish()
         torch.cuda.synchronize()
