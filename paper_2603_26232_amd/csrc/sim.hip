@@ -510,9 +510,37 @@ struct CutTab {
     __device__ uint32_t at(uint32_t i) const { return w == 1 ? (uint32_t)p[i] : (uint32_t)((const uint16_t*)p)[i]; }
 };
 
-template <int L>
-__device__ inline void load_cut_L(uint16_t (&cr)[REGS], const CutTab& tab, uint32_t tid, uint32_t m)
+template <int L, bool G0 = false, typename T = uint16_t>
+__device__ inline void load_cut_L(T (&cr)[REGS], const CutTab& tab, uint32_t tid, uint32_t m)
 {
+    if constexpr (G0) {
+        // group 0 flips all twelve tile bits or none, so the register bits
+        // of m are all set or all clear: the per-register offsets are then
+        // constants, in one of two orders chosen by a uniform branch
+        constexpr uint32_t R = reg_part<L>(REGS - 1);
+        const uint32_t base = (thread_part<L>(tid) ^ m) & ~R;
+        const bool rev = (m & R) != 0u;
+        if (tab.w == 1) {
+            const uint8_t* p = tab.p + base;
+            if (rev) {
+#pragma unroll
+                for (int r = 0; r < REGS; ++r) cr[r] = p[reg_part<L>(REGS - 1 - r)];
+            } else {
+#pragma unroll
+                for (int r = 0; r < REGS; ++r) cr[r] = p[reg_part<L>(r)];
+            }
+        } else {
+            const uint16_t* p = (const uint16_t*)tab.p + base;
+            if (rev) {
+#pragma unroll
+                for (int r = 0; r < REGS; ++r) cr[r] = p[reg_part<L>(REGS - 1 - r)];
+            } else {
+#pragma unroll
+                for (int r = 0; r < REGS; ++r) cr[r] = p[reg_part<L>(r)];
+            }
+        }
+        return;
+    }
     const uint32_t tp = thread_part<L>(tid) ^ m;
     if (tab.w == 1) {
 #pragma unroll
@@ -824,7 +852,7 @@ enum { B_FUSED = 0, B_SINGLE = 1, B_MID = 2, B_LAST = 3 };
 // The fused kind on group 0 is held to four waves per SIMD (the most that
 // its LDS tile allows); left free, it takes 130 registers and runs three.
 template <int CH, bool FULL, int KIND, bool STORE_PSI = true>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND == B_FUSED && CH == 3 ? 4 : PQ_BWD_WAVES))) void k_bwd_pass(
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu((KIND == B_FUSED || KIND == B_LAST) && CH == 3 ? 4 : PQ_BWD_WAVES))) void k_bwd_pass(
     uint8_t* ws, const SubDesc* subs, const int2* work, PassOps ops, Partials part)
 {
     extern __shared__ float2 smem[];
@@ -862,36 +890,63 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(KIND ==
             lut[i] = cmul(make_float2(e.x, -e.y), F);
         }
     } else if constexpr (KIND == B_LAST) {
-        // the phase table of layer 1 as the forward pass used it
+        // the phase table of layer 1 as the forward pass used it, times the
+        // amplitude 2^(-(n-1)/2) of the stored |+> and the conjugate of the
+        // inverse factor of RX(pre): every sum of this pass is bilinear in
+        // conj(lambda) and psi, so scaling psi by conj(Fi) stands for scaling
+        // lambda by Fi
         const float2* L = (const float2*)(ws + sd->lut) + (size_t)ops.ph * lut_len;
-        for (int i = tid; i < lut_len; i += THREADS) lut[i] = L[i];
+        const float amp = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
+        const float2 F = make_float2(amp * pre.Fi.x, -amp * pre.Fi.y);
+        for (int i = tid; i < lut_len; i += THREADS) lut[i] = cmul(L[i], F);
     }
+    // the last kind synthesises psi in every layout of the chain from the
+    // cut values of that layout (group 0 only: its chain is LLIN, LL0, LL1),
+    // instead of moving psi through LDS with lambda
+    constexpr bool SYNTH = KIND == B_LAST && CH == 3;
     // the cut values (used after the first segment) are loaded with the
     // states, so their latency is hidden behind that segment
     uint16_t cr[REGS];
-    if constexpr (KIND != B_SINGLE) load_cut_L<LE>(cr, tab, tid, m_pre);
+    if constexpr (KIND != B_SINGLE) load_cut_L<LE, SYNTH>(cr, tab, tid, m_pre);
+    uint32_t cr0[SYNTH ? REGS : 1], crI[SYNTH ? REGS : 1];
+    if constexpr (SYNTH) {
+        load_cut_L<LL0, true>(cr0, tab, tid, m_pre);
+        load_cut_L<LLIN, true>(crI, tab, tid, m_pre);
+    }
     float2 ps[REGS], la[REGS];
-    // the middle kind (the busiest vector units) uses the one-XOR offsets
-    constexpr bool O32 = KIND == B_MID;
+    // the kinds with the busiest vector units use the one-XOR offsets
+    constexpr bool O32 = KIND == B_MID || KIND == B_LAST;
     if constexpr (KIND != B_LAST) load_state<LS, CH == 3, O32>(ps, sp, geo, tid);
     if constexpr (KIND != B_FUSED) load_state<LS, CH == 3, O32>(la, sl, geo, tid);
     __syncthreads();
     double acc_pre = 0.0, acc_ph = 0.0, acc_post = 0.0, acc_e = 0.0;
     if constexpr (KIND == B_LAST) {
-        // lambda back through RX(pre); slot q then holds amplitude q ^ m_pre
+        // lambda back through RX(pre) (its factor Fi is in the table); slot q
+        // then holds amplitude q ^ m_pre
         seg_rot<CH, FULL, true>(la, lds, geo.c, -pre.t, tid);
-        scale_regs(la, pre.Fi);
-        const float amp = (float)(1.0 / sqrt((double)(1ull << (sd->n - 1))));
         float a = 0.f;
 #pragma unroll
         for (int r = 0; r < REGS; ++r) {
-            const float2 f = lut[cr[r]];
-            ps[r] = make_float2(amp * f.x, amp * f.y);
+            ps[r] = lut[cr[r]];
             // C(z) Im(conj(lambda) psi)
             a = fmaf((float)cr[r], fmaf(la[r].x, ps[r].y, -la[r].y * ps[r].x), a);
         }
         acc_ph = (double)a;
-        seg_xb<CH, FULL, false>(ps, la, lds, geo.c, tid, acc_pre);
+        if constexpr (SYNTH) {
+            // the beta terms in the three layouts, lambda walking back LL1 ->
+            // LL0 -> LLIN and psi synthesised afresh in each
+            acc_pre += (double)xb_round<LL1, FULL>(ps, la, geo.c);
+            xchg<LL1, LL0>(lds, tid, la);
+#pragma unroll
+            for (int r = 0; r < REGS; ++r) ps[r] = lut[cr0[r]];
+            acc_pre += (double)xb_round<LL0, FULL>(ps, la, geo.c);
+            xchg<LL0, LLIN>(lds, tid, la);
+#pragma unroll
+            for (int r = 0; r < REGS; ++r) ps[r] = lut[crI[r]];
+            acc_pre += (double)xb_round<LLIN, FULL>(ps, la, geo.c);
+        } else {
+            seg_xb<CH, FULL, false>(ps, la, lds, geo.c, tid, acc_pre);
+        }
     } else if constexpr (KIND == B_FUSED) {
         // psi_p = RX(pre) psi (slot q then holds amplitude q ^ m_pre)
         seg_rot<CH, FULL, true>(ps, lds, geo.c, pre.t, tid);
