@@ -153,7 +153,8 @@ def workload_solve(args, name):
     cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
     log(f"bench: graph {g}, {part.M} subgraphs of sizes {min(part.size)}..{max(part.size)}, p={cfg.p}, "
         f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
-    S = Solver(g, part, cfg, skip_edgeless=skip, gradient_memory=args.gradient_memory)
+    S = Solver(g, part, cfg, skip_edgeless=skip, gradient_memory=args.gradient_memory,
+               concurrent_classes=args.concurrent_classes)
     from paper_2603_26232_amd import _abi
     ckpt = _abi.qaoa_gradient_checkpoints(S.batch.handle)
     nE = np.array([len(e[0]) for e in S.sub_edges])
@@ -273,7 +274,7 @@ def workload_solve(args, name):
                                "sample": f"every 4th subgraph of that sample ({len(one)}), {T1} Adam steps + "
                                          f"final evaluation"}}
 
-    config = {"workload": desc, "merge_overlaps_next_solve": overlap,
+    config = {"workload": desc, "merge_overlaps_next_solve": overlap, "concurrent_classes": args.concurrent_classes,
               "gradient_memory": ("forward checkpoints" if ckpt else "in place") + f" ({args.gradient_memory})",
               "vertices": g.num_vertices, "edges": g.num_edges,
               "subgraphs": part.M, "simulated_subgraphs": len(sim),
@@ -351,6 +352,8 @@ def main():
                     help="solve workloads: skip the plain solves with the Adam loop replayed from a HIP graph")
     ap.add_argument("--gradient-memory", choices=["auto", "checkpoints", "inplace"], default="auto",
                     help="forward checkpoints, one psi rebuilt in place, or the library's choice by size")
+    ap.add_argument("--concurrent-classes", action="store_true",
+                    help="run the qubit-group classes of the batch concurrently on side streams")
     ap.add_argument("--tuning", default="default",
                     help="group-split tuning table (JSON from paper_2603_26232_amd.autotune); 'default' = the "
                          "package's table if present, 'none' = untuned")

@@ -106,6 +106,22 @@ typedef void* qaoa_stream_t;
  * a batch uses. */
 #define QAOA_FLAG_GRADIENT_INPLACE 0x40u
 #define QAOA_FLAG_GRADIENT_CHECKPOINTS 0x80u
+/* Run the qubit-group classes of a ragged batch concurrently (Sec. 3.3: the
+ * subgraph solvers are independent). The tiles of all subgraphs with the same
+ * qubit-group layout form a class, and each class runs its own sequence of
+ * HBM passes; by default the classes run one after another on the caller's
+ * stream. With this flag, qaoa_apply_layers, qaoa_expectation_grad and
+ * qaoa_optimize keep the class of the largest subgraphs on the caller's
+ * stream and give the other classes and the small-subgraph kernel to three
+ * side streams of the library, forked from and joined back to the caller's
+ * stream with events within each call (each Adam step of qaoa_optimize), so
+ * that the smaller classes fill the device while the largest one runs.
+ * Results are bit-identical to the default. The side streams and events are
+ * created once per device (default priority) by the first qaoa_batch_create
+ * with this flag, with that device current, and are kept until the process
+ * ends; batches on one device share them, and their enqueues are serialised
+ * by a lock. The calls stay capturable into a HIP graph. */
+#define QAOA_FLAG_CONCURRENT_CLASSES 0x100u
 
 /* Workspace size for a batch (paper Sec. 3.3: the subgraphs {G[V_i]} that
  * Alg. 1 produces, each solved by its own QAOA instance).

@@ -24,6 +24,7 @@ QAOA_FLAG_MIXER_MFMA_BF16X3 = 0x10
 QAOA_FLAG_MIXER_MFMA_BF16X4 = 0x20
 QAOA_FLAG_GRADIENT_INPLACE = 0x40
 QAOA_FLAG_GRADIENT_CHECKPOINTS = 0x80
+QAOA_FLAG_CONCURRENT_CLASSES = 0x100
 QAOA_MAX_QUBITS = 30
 QAOA_MAX_DEPTH = 32
 QAOA_MAX_K = 64

@@ -29,7 +29,8 @@ class QaoaBatch:
                        "inplace": _abi.QAOA_FLAG_GRADIENT_INPLACE}
 
     def __init__(self, sizes, sub_edges, max_p, max_k=16, gradient=False, raw_topk=False,
-                 skip_edgeless=False, device="cuda", stream=None, mixer="valu", gradient_memory="auto"):
+                 skip_edgeless=False, device="cuda", stream=None, mixer="valu", gradient_memory="auto",
+                 concurrent_classes=False):
         nq, off, u, v, w = batch_arrays(sizes, sub_edges)
         self.B = int(nq.shape[0])
         self.sizes = nq
@@ -38,7 +39,8 @@ class QaoaBatch:
         self.device = torch.device(device)
         flags = ((_abi.QAOA_FLAG_GRADIENT if gradient else 0) | (_abi.QAOA_FLAG_TOPK_RAW if raw_topk else 0)
                  | (_abi.QAOA_FLAG_SKIP_EDGELESS if skip_edgeless else 0) | self.MIXERS[mixer]
-                 | self.GRADIENT_MEMORY[gradient_memory])
+                 | self.GRADIENT_MEMORY[gradient_memory]
+                 | (_abi.QAOA_FLAG_CONCURRENT_CLASSES if concurrent_classes else 0))
         self.flags = flags
         nbytes = _abi.qaoa_workspace_bytes(self.B, nq, off, w, self.max_p, self.max_k, flags)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

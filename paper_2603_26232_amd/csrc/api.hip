@@ -266,7 +266,7 @@ qaoa_status_t make_plan(int32_t B, const int32_t* nq, const int64_t* eoff, const
     const uint32_t mixer =
         flags & (QAOA_FLAG_MIXER_MFMA_F32 | QAOA_FLAG_MIXER_MFMA_BF16X3 | QAOA_FLAG_MIXER_MFMA_BF16X4);
     if (flags & ~(QAOA_FLAG_GRADIENT | QAOA_FLAG_TOPK_RAW | QAOA_FLAG_SKIP_EDGELESS | QAOA_FLAG_GRADIENT_INPLACE |
-                  QAOA_FLAG_GRADIENT_CHECKPOINTS | mixer))
+                  QAOA_FLAG_GRADIENT_CHECKPOINTS | QAOA_FLAG_CONCURRENT_CLASSES | mixer))
         return fail(QAOA_ERR_INVALID_ARG, "unknown flag bits 0x%x", flags);
     if ((flags & QAOA_FLAG_GRADIENT_INPLACE) && (flags & QAOA_FLAG_GRADIENT_CHECKPOINTS))
         return fail(QAOA_ERR_INVALID_ARG, "QAOA_FLAG_GRADIENT_INPLACE and QAOA_FLAG_GRADIENT_CHECKPOINTS together");
@@ -558,6 +558,41 @@ extern "C" qaoa_status_t qaoa_tune_group_split(int32_t n, int32_t count, const i
 }
 
 // ---------------------------------------------------------------------------
+// side streams of the concurrent-classes mode: per device, created once
+// (default priority) and kept until the process ends; one lock serialises the
+// fork/join sequences of all batches, so the shared events are never
+// re-recorded before the waits that read them are enqueued
+// ---------------------------------------------------------------------------
+constexpr int NSIDE = 3;
+constexpr int SIDE_MAX_DEVICES = 64;
+struct SideStreams {
+    hipStream_t s[NSIDE];
+    hipEvent_t fork;
+    hipEvent_t join[NSIDE];
+};
+std::mutex g_side_mu;
+SideStreams* g_side[SIDE_MAX_DEVICES] = {};
+
+static qaoa_status_t side_streams(SideStreams** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SIDE_MAX_DEVICES) return fail(QAOA_ERR_NOT_SUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev]) {
+        SideStreams* ss = new SideStreams();
+        for (int j = 0; j < NSIDE; ++j) {
+            HIP_TRY(hipStreamCreateWithFlags(&ss->s[j], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&ss->join[j], hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventCreateWithFlags(&ss->fork, hipEventDisableTiming));
+        g_side[dev] = ss;
+    }
+    *out = g_side[dev];
+    return QAOA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
 struct qaoa_batch_s {
@@ -565,9 +600,57 @@ struct qaoa_batch_s {
     uint8_t* ws = nullptr;
     SubDesc* d_subs = nullptr;
     Partials part{};
-    bool state_valid = false;  // psi holds the ansatz state of the last apply
-    bool e_valid = false;      // <C> partials are fresh
+    SideStreams* side = nullptr;  // set with QAOA_FLAG_CONCURRENT_CLASSES
+    bool state_valid = false;     // psi holds the ansatz state of the last apply
+    bool e_valid = false;         // <C> partials are fresh
 };
+
+// Runs body(class index or -1 for the small-subgraph kernel, stream) for the
+// small-subgraph kernel (if any) and every class. Default: all on st, in
+// order. Concurrent classes: class 0 (the largest subgraphs) on st, the rest
+// each on the side stream with the least work so far (tiles x passes),
+// forked from st and joined back into it.
+template <typename F>
+static qaoa_status_t for_each_class(qaoa_batch_t h, int32_t p, hipStream_t st, F body)
+{
+    const Plan& P = h->P;
+    const int nc = (int)P.classes.size();
+    if (!h->side || nc + (P.nsmall ? 1 : 0) < 2) {
+        qaoa_status_t s;
+        if (P.nsmall && (s = body(-1, st)) != QAOA_OK) return s;
+        for (int k = 0; k < nc; ++k)
+            if ((s = body(k, st)) != QAOA_OK) return s;
+        return QAOA_OK;
+    }
+    SideStreams& ss = *h->side;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    HIP_TRY(hipEventRecord(ss.fork, st));
+    double load[NSIDE] = {};
+    bool used[NSIDE] = {};
+    auto pick = [&](double w) -> hipStream_t {
+        int j = 0;
+        for (int i = 1; i < NSIDE; ++i)
+            if (load[i] < load[j]) j = i;
+        load[j] += w;
+        if (!used[j]) {
+            used[j] = true;
+            (void)hipStreamWaitEvent(ss.s[j], ss.fork, 0);
+        }
+        return ss.s[j];
+    };
+    qaoa_status_t s = QAOA_OK;
+    if (nc > 0) s = body(0, st);
+    for (int k = 1; k < nc && s == QAOA_OK; ++k)
+        s = body(k, pick((double)P.classes[k].work.size() * (double)(p * (P.classes[k].G - 1) + 1)));
+    if (P.nsmall && s == QAOA_OK) s = body(-1, pick((double)P.nsmall * p));
+    // join every side stream that was forked, also after an error
+    for (int j = 0; j < NSIDE; ++j) {
+        if (!used[j]) continue;
+        (void)hipEventRecord(ss.join[j], ss.s[j]);
+        (void)hipStreamWaitEvent(st, ss.join[j], 0);
+    }
+    return s;
+}
 
 extern "C" const char* qaoa_status_string(qaoa_status_t s)
 {
@@ -651,7 +734,13 @@ extern "C" qaoa_status_t qaoa_batch_create(int32_t B, const int32_t* num_qubits,
     s = upload_async(ws, img.data(), meta_end, st);
     if (s != QAOA_OK) return s;
 
+    SideStreams* side = nullptr;
+    if (flags & QAOA_FLAG_CONCURRENT_CLASSES) {
+        s = side_streams(&side);
+        if (s != QAOA_OK) return s;
+    }
     qaoa_batch_s* h = new qaoa_batch_s();
+    h->side = side;
     h->P = std::move(P);
     h->ws = ws;
     h->d_subs = (SubDesc*)(ws + h->P.o_subs);
@@ -699,12 +788,14 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
         ProfScope ps("angle_prep", st, angle_bytes(P, p));
         HIP_TRY(launch_angle_prep(h->ws, h->d_subs, P.B, p, d_gamma, d_beta, st));
     }
-    if (P.nsmall) {
-        ProfScope ps("small", st, small_bytes(P, p, false));
-        HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 0, h->part,
-                             P.lut_max, st));
-    }
-    for (const auto& c : P.classes) {
+    s = for_each_class(h, p, st, [&](int k, hipStream_t cs) -> qaoa_status_t {
+        if (k < 0) {
+            ProfScope ps("small", cs, small_bytes(P, p, false));
+            HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 0, h->part,
+                                 P.lut_max, cs));
+            return QAOA_OK;
+        }
+        const auto& c = P.classes[k];
         const int2* work = (const int2*)(h->ws + c.o_work);
         const int nw = (int)c.work.size();
         std::vector<PassOps> passes = group_passes(forward_ops(c.G, p));
@@ -712,11 +803,13 @@ extern "C" qaoa_status_t qaoa_apply_layers(qaoa_batch_t h, int32_t p, const doub
             PassOps o = passes[i];
             o.init = i == 0;
             o.epi_e = i + 1 == passes.size();
-            ProfScope ps(pass_name(o, false), st, pass_bytes(o, false, nw, c.tab_bytes));
+            ProfScope ps(pass_name(o, false), cs, pass_bytes(o, false, nw, c.tab_bytes));
             HIP_TRY(launch_fwd_pass(h->ws, h->d_subs, work, nw, c.chain[o.group], o, h->part, P.lut_max, P.prec,
-                                    st));
+                                    cs));
         }
-    }
+        return QAOA_OK;
+    });
+    if (s != QAOA_OK) return s;
     h->state_valid = true;
     h->e_valid = true;
     return ok();
@@ -751,17 +844,19 @@ extern "C" qaoa_status_t qaoa_topk(qaoa_batch_t h, int32_t k, uint32_t* d_idx, f
     return ok();
 }
 
-// the small-subgraph kernel and every tile pass of one gradient evaluation
-// (forward sweep, fused turn, adjoint sweep), after the angle tables are set
-static qaoa_status_t enqueue_grad_passes(qaoa_batch_t h, int32_t p, hipStream_t st)
+// one class's tile passes of a gradient evaluation (forward sweep, fused
+// turn, adjoint sweep), or the small-subgraph kernel (k < 0)
+static qaoa_status_t enqueue_class_grad(qaoa_batch_t h, int k, int32_t p, hipStream_t st)
 {
     Plan& P = h->P;
-    if (P.nsmall) {
+    if (k < 0) {
         ProfScope ps("small", st, small_bytes(P, p, true));
         HIP_TRY(launch_small(h->ws, h->d_subs, (const int32_t*)(h->ws + P.o_small), P.nsmall, p, 1, h->part,
                              P.lut_max, st));
+        return QAOA_OK;
     }
-    for (const auto& c : P.classes) {
+    {
+        const auto& c = P.classes[k];
         const int2* work = (const int2*)(h->ws + c.o_work);
         const int nw = (int)c.work.size();
         std::vector<Op> ops = forward_ops(c.G, p);
@@ -801,6 +896,13 @@ static qaoa_status_t enqueue_grad_passes(qaoa_batch_t h, int32_t p, hipStream_t 
         }
     }
     return QAOA_OK;
+}
+
+// the small-subgraph kernel and every tile pass of one gradient evaluation
+// (forward sweep, fused turn, adjoint sweep), after the angle tables are set
+static qaoa_status_t enqueue_grad_passes(qaoa_batch_t h, int32_t p, hipStream_t st)
+{
+    return for_each_class(h, p, st, [&](int k, hipStream_t cs) { return enqueue_class_grad(h, k, p, cs); });
 }
 
 extern "C" qaoa_status_t qaoa_expectation_grad(qaoa_batch_t h, int32_t p, const double* d_gamma,

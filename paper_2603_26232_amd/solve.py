@@ -57,7 +57,7 @@ class Solver:
     nothing new (the bench times `run`)."""
 
     def __init__(self, graph, part: Partition, cfg: SolveConfig, device="cuda", skip_edgeless=False,
-                 gradient_memory="auto"):
+                 gradient_memory="auto", concurrent_classes=False):
         self.g = graph
         self.part = part
         self.cfg = cfg
@@ -66,7 +66,8 @@ class Solver:
         self.B = part.M
         dev = self.device
         self.batch = QaoaBatch(part.size, self.sub_edges, max_p=cfg.p, max_k=cfg.k, gradient=True,
-                               skip_edgeless=skip_edgeless, device=dev, gradient_memory=gradient_memory)
+                               skip_edgeless=skip_edgeless, device=dev, gradient_memory=gradient_memory,
+                               concurrent_classes=concurrent_classes)
         P = self.B * cfg.p
         self.theta = torch.zeros(2 * P, dtype=torch.float64, device=dev)   # [gamma | beta]
         self._theta_host = torch.zeros(2 * P, dtype=torch.float64, pin_memory=dev.type == "cuda")

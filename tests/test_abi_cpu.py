@@ -54,7 +54,7 @@ def test_argument_errors():
         _ws([5], [e], max_k=65)
     assert ei.value.status == 2
     with pytest.raises(_abi.QaoaError) as ei:
-        _ws([5], [e], flags=0x100)  # an unknown flag bit
+        _ws([5], [e], flags=0x200)  # an unknown flag bit
     assert ei.value.status == 1
     heavy = (np.array([0], np.int32), np.array([1], np.int32), np.array([5000], np.int32))
     with pytest.raises(_abi.QaoaError) as ei:
