@@ -56,6 +56,9 @@ def test_argument_errors():
     with pytest.raises(_abi.QaoaError) as ei:
         _ws([5], [e], flags=0x200)  # an unknown flag bit
     assert ei.value.status == 1
+    # the concurrent-classes flag is known and changes no workspace size
+    assert _ws([5, 20, 23], [e] * 3, flags=_abi.QAOA_FLAG_GRADIENT | _abi.QAOA_FLAG_CONCURRENT_CLASSES) == \
+        _ws([5, 20, 23], [e] * 3, flags=_abi.QAOA_FLAG_GRADIENT)
     heavy = (np.array([0], np.int32), np.array([1], np.int32), np.array([5000], np.int32))
     with pytest.raises(_abi.QaoaError) as ei:
         _ws([5], [heavy])
