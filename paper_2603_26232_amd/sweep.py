@@ -93,9 +93,14 @@ def main():
                     choices=list(WORKLOADS))
     ap.add_argument("--K", type=int, nargs="+", default=[1, 2, 4, 8, 16])
     ap.add_argument("--W", type=int, nargs="+", default=[1, 16, 64, 256, 1024, 4096, 8192])
+    ap.add_argument("--tuning", default="default",
+                    help="group-split table to apply: 'default' (the package's), 'none', or a path")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, flush=True)
+    if args.tuning != "none":
+        from . import autotune
+        autotune.apply(autotune.DEFAULT_TABLE if args.tuning == "default" else args.tuning)
     res = [sweep(w, args.K, args.W, log=log) for w in args.workload]
     with open(os.path.join(args.out, "merge_sweep.json"), "w") as f:
         json.dump(res, f, indent=1)

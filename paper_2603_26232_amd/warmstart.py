@@ -160,9 +160,14 @@ def main():
     ap.add_argument("--model", default=None, help="load a trained model (.npz) instead of training")
     ap.add_argument("--eval", choices=["c3", "c5", "both", "none"], default="both")
     ap.add_argument("--T-max", type=int, default=200)
+    ap.add_argument("--tuning", default="default",
+                    help="group-split table to apply: 'default' (the package's), 'none', or a path")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     log = lambda *a: print(*a, flush=True)
+    if args.tuning != "none":
+        from . import autotune
+        autotune.apply(autotune.DEFAULT_TABLE if args.tuning == "default" else args.tuning)
     p = 3
     model = AnglePredictor(p, seed=0)
     result = {}
