@@ -54,6 +54,26 @@ def test_batch_calls_bit_identical(memory):
     con.close()
 
 
+@pytest.mark.parametrize("mixer", ["mfma_f32", "mfma_bf16x4"])
+def test_forward_matrix_core_modes_bit_identical(mixer):
+    """Forward-only batches with a matrix-core mixer mode (their group-0
+    passes are another kernel family) give the same states, <C> and top-k."""
+    edges = _edges(SIZES, 60)
+    gamma, beta = synth.uniform_angles(61, 2, batch=len(SIZES))
+    out = []
+    for conc in (False, True):
+        bt = QaoaBatch(SIZES, edges, max_p=2, max_k=8, mixer=mixer, concurrent_classes=conc)
+        bt.apply_layers(gamma, beta)
+        E = bt.expectation().clone()
+        idx, prob = bt.topk(8)
+        st = [bt.reduced_state(b).clone() for b in range(len(SIZES))]
+        torch.cuda.synchronize()
+        out.append([E, idx.clone(), prob.clone()] + st)
+        bt.close()
+    for i, (a, b) in enumerate(zip(*out)):
+        assert torch.equal(a, b), i
+
+
 def _ragged():
     g = synth.erdos_renyi(240, 0.05, 11)
     part = partition_chain(240, synth.ragged_sizes(3, 10, 22, 240))
