@@ -193,27 +193,50 @@ def workload_solve(args, name):
     def summary():
         return {"solve": result()}
 
+    n_cmp = max(3, args.steps // 2)
+
     def graph_compare(plain_s, ref):
         """The same plain solves with the 50 Adam steps replayed from one
         captured HIP graph (captured by the first, untimed solve)."""
-        log(f"bench: plain solves with the {cfg.iters}-step Adam loop in one HIP graph, {args.steps} timed")
+        log(f"bench: plain solves with the {cfg.iters}-step Adam loop in one HIP graph, {n_cmp} timed")
         c0 = time.perf_counter()
         graph_step()
         torch.cuda.synchronize()
         first = time.perf_counter() - c0
-        gs = time_solves(graph_step, args.steps)
+        gs = time_solves(graph_step, n_cmp)
         r = result()
         log(f"bench: graph replay {gs:.4f} s/solve (eager {plain_s:.4f}), first solve with capture {first:.2f} s")
         return {"seconds": round(gs, 4), "eager_seconds": round(plain_s, 4), "speedup_vs_eager": round(plain_s / gs, 4),
                 "first_solve_with_capture_seconds": round(first, 3), "same_result_as_eager": r == ref}
 
+    def concurrent_compare(plain_s, ref):
+        """The same plain solves with the qubit-group classes on concurrent
+        side streams (the batch re-created with the flag, same workspace);
+        kernel timings overlap there, so the roofline stays serial."""
+        log(f"bench: plain solves with concurrent classes, {n_cmp} timed")
+        S.batch.flags |= _abi.QAOA_FLAG_CONCURRENT_CLASSES
+        try:
+            step()
+            cs = time_solves(step, n_cmp)
+            r = result()
+        finally:
+            # the next solve's batch build drops the flag again
+            S.batch.flags &= ~_abi.QAOA_FLAG_CONCURRENT_CLASSES
+        log(f"bench: concurrent classes {cs:.4f} s/solve (serial {plain_s:.4f})")
+        return {"seconds": round(cs, 4), "serial_seconds": round(plain_s, 4),
+                "speedup_vs_serial": round(plain_s / cs, 4), "same_result_as_serial": r == ref}
+
     def extra(plain_s):
         """After the timed plain solves: their result, the plain solves with
-        the Adam loop replayed from a HIP graph, the learned solves timed the
-        same way, and the latency of one solve of each kind."""
+        the Adam loop replayed from a HIP graph and with concurrent classes,
+        the learned solves timed the same way, and the latency of one solve
+        of each kind."""
         out = {"plain": dict(result(), seconds=round(plain_s, 4), adam_steps=cfg.iters, adam_lr=cfg.lr)}
         if not args.no_graph_compare:
             out["plain_graph_replay"] = graph_compare(plain_s, result())
+        if not args.concurrent_classes and not args.no_concurrent_compare:
+            ref = {k: out["plain"][k] for k in ("cut", "sum_E_with_edges")}
+            out["plain_concurrent_classes"] = concurrent_compare(plain_s, ref)
         if LS is None:
             return {"solve": out}
         log(f"bench: learned-warm-start solves ({args.warm_iters} Adam steps), {args.steps} timed")
@@ -354,6 +377,8 @@ def main():
                     help="forward checkpoints, one psi rebuilt in place, or the library's choice by size")
     ap.add_argument("--concurrent-classes", action="store_true",
                     help="run the qubit-group classes of the batch concurrently on side streams")
+    ap.add_argument("--no-concurrent-compare", action="store_true",
+                    help="solve workloads: skip the plain solves with concurrent classes")
     ap.add_argument("--tuning", default="default",
                     help="group-split tuning table (JSON from paper_2603_26232_amd.autotune); 'default' = the "
                          "package's table if present, 'none' = untuned")
