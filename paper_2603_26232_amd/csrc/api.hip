@@ -627,6 +627,10 @@ static qaoa_status_t for_each_class(qaoa_batch_t h, int32_t p, hipStream_t st, F
     HIP_TRY(hipEventRecord(ss.fork, st));
     double load[NSIDE] = {};
     bool used[NSIDE] = {};
+    hipError_t ferr = hipSuccess;  // first failure of a fork or join call
+    auto note = [&](hipError_t e) {
+        if (e != hipSuccess && ferr == hipSuccess) ferr = e;
+    };
     auto pick = [&](double w) -> hipStream_t {
         int j = 0;
         for (int i = 1; i < NSIDE; ++i)
@@ -634,21 +638,23 @@ static qaoa_status_t for_each_class(qaoa_batch_t h, int32_t p, hipStream_t st, F
         load[j] += w;
         if (!used[j]) {
             used[j] = true;
-            (void)hipStreamWaitEvent(ss.s[j], ss.fork, 0);
+            note(hipStreamWaitEvent(ss.s[j], ss.fork, 0));
         }
         return ss.s[j];
     };
     qaoa_status_t s = QAOA_OK;
     if (nc > 0) s = body(0, st);
-    for (int k = 1; k < nc && s == QAOA_OK; ++k)
+    for (int k = 1; k < nc && s == QAOA_OK && ferr == hipSuccess; ++k)
         s = body(k, pick((double)P.classes[k].work.size() * (double)(p * (P.classes[k].G - 1) + 1)));
-    if (P.nsmall && s == QAOA_OK) s = body(-1, pick((double)P.nsmall * p));
+    if (P.nsmall && s == QAOA_OK && ferr == hipSuccess) s = body(-1, pick((double)P.nsmall * p));
     // join every side stream that was forked, also after an error
     for (int j = 0; j < NSIDE; ++j) {
         if (!used[j]) continue;
-        (void)hipEventRecord(ss.join[j], ss.s[j]);
-        (void)hipStreamWaitEvent(st, ss.join[j], 0);
+        note(hipEventRecord(ss.join[j], ss.s[j]));
+        note(hipStreamWaitEvent(st, ss.join[j], 0));
     }
+    if (s == QAOA_OK && ferr != hipSuccess)
+        return fail(QAOA_ERR_HIP, "fork/join of the concurrent classes: %s", hipGetErrorString(ferr));
     return s;
 }
 
