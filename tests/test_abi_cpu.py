@@ -45,6 +45,13 @@ def test_qubit_range(n, status):
     assert ei.value.status == status
 
 
+def test_empty_batch_is_rejected():
+    with pytest.raises(_abi.QaoaError) as ei:
+        _abi.qaoa_workspace_bytes(0, np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32), 3, 16, 0)
+    assert ei.value.status == 1
+    assert "B = 0" in str(ei.value)
+
+
 def test_argument_errors():
     e = (np.array([0], np.int32), np.array([1], np.int32), np.array([1], np.int32))
     with pytest.raises(_abi.QaoaError) as ei:
