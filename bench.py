@@ -23,6 +23,9 @@ are reported.
 Other workloads (--workload):
   plain400     the same plain solve on G(400, 0.05), seed 0, 21 subgraphs of
                20 vertices (equal partition, stride 19).
+  learned16000 the plain and the learned-warm-start solves of G(16000, 0.001),
+               seed 0, chained into ragged subgraphs of 20..24 vertices
+               (sizes from stream seed 1; 764 subgraphs, 148 with edges).
   precision26  one forward evaluation (all layers + <C>) of 32 random 3-regular
                graphs on 26 vertices, p = 4, angles U(0, pi); --mixer picks the
                mixer precision mode.
@@ -128,8 +131,9 @@ def time_solves(run, n, sync_each=False):
 
 
 def workload_solve(args, name):
-    """plain400 / ragged2000: the plain-method solve as one step; ragged2000
-    also times the learned-warm-start solve of the same graph."""
+    """plain400 / ragged2000 / learned16000: the plain-method solve as one
+    step; the ragged workloads also time the learned-warm-start solve of the
+    same graph."""
     import numpy as np
     import torch
     from paper_2603_26232_amd import synth
@@ -142,6 +146,14 @@ def workload_solve(args, name):
         skip = False
         desc = "plain-method solve, G(400,0.05) seed 0, 21 subgraphs x 20 qubits, p=3, 50 Adam steps, top-16, " \
                "beam 4096, CutVal"
+    elif name == "learned16000":
+        g = synth.erdos_renyi(16000, 0.001, 0)
+        part = partition_chain(16000, synth.ragged_sizes(1, 20, 24, 16000))
+        skip = True
+        desc = "16k-vertex solve: G(16000,0.001) seed 0, ragged chain of 20..24-qubit subgraphs, edgeless " \
+               "skipped, p=3, top-16, beam 4096, CutVal; plain = cold start + 50 Adam steps, learned = " \
+               f"predicted start (cold-start fallback per subgraph) + {args.warm_iters} Adam steps at step size " \
+               f"{args.warm_lr}"
     else:
         g = synth.erdos_renyi(2000, 0.01, 0)
         part = partition_chain(2000, synth.ragged_sizes(1, 14, 26, 2000))
@@ -164,7 +176,7 @@ def workload_solve(args, name):
     overlap = not args.no_overlap
 
     LS = None
-    if name == "ragged2000" and not args.no_learned:
+    if name in ("ragged2000", "learned16000") and not args.no_learned:
         from paper_2603_26232_amd.learned import AnglePredictor, LearnedStart
         model = AnglePredictor.from_file(args.predictor)
         LS = LearnedStart(S, model)
@@ -260,12 +272,15 @@ def workload_solve(args, name):
 
     def cpu_baseline():
         import oracle
-        # bounded sample: every subgraph (plain400) or every 2nd simulated
-        # subgraph of at most 22 qubits (ragged2000), T Adam steps with the
-        # final evaluation; then a quarter of it on one thread
+        # bounded sample: every subgraph (plain400) or every 2nd (ragged2000)
+        # or 6th (learned16000, all of 20 qubits or more) simulated subgraph of
+        # at most 22 qubits, T Adam steps with the final evaluation; then a
+        # quarter of it on one thread
+        every = 6 if name == "learned16000" else 2
         idx = list(range(part.M)) if name == "plain400" else \
-            [b for b in range(part.M) if not (skip and nE[b] == 0) and part.size[b] <= 22][::2]
-        which = "all" if name == "plain400" else "every 2nd simulated one of at most 22 qubits"
+            [b for b in range(part.M) if not (skip and nE[b] == 0) and part.size[b] <= 22][::every]
+        which = "all" if name == "plain400" else f"every {every}th simulated one of at most 22 qubits".replace(
+            "2th", "2nd")
         T = args.cpu_iters
 
         def timed(ids, T):
@@ -359,13 +374,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["ragged2000", "plain400", "precision26"], default="ragged2000")
+    ap.add_argument("--workload", choices=["ragged2000", "learned16000", "plain400", "precision26"],
+                    default="ragged2000")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run each solve's merge on the main stream instead of overlapping it with the next solve")
     ap.add_argument("--mixer", choices=["valu", "mfma_f32", "mfma_bf16x3", "mfma_bf16x4"], default="valu",
                     help="mixer precision mode (precision26 only)")
     ap.add_argument("--cpu-iters", type=int, default=12, help="Adam steps in the CPU-baseline sample")
-    ap.add_argument("--no-learned", action="store_true", help="ragged2000: skip the learned-warm-start solves")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="ragged workloads: skip the learned-warm-start solves")
     ap.add_argument("--warm-iters", type=int, default=5, help="Adam steps of a learned-warm-start solve")
     ap.add_argument("--warm-lr", type=float, default=0.02, help="Adam step size of a learned-warm-start solve")
     ap.add_argument("--predictor", default=None, help="trained angle predictor (.npz); default: the package's")
