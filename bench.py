@@ -10,7 +10,12 @@ chain of ragged subgraphs of 14..26 vertices (sizes from stream seed 1);
 edgeless subgraphs are not simulated (closed form); QAOA depth p = 3.
 Consecutive solves are pipelined: a solve's merge and CutVal run on a second
 stream while the next solve starts (--no-overlap runs them in line); the timed
-region still ends when every solve's merge has finished.
+region still ends when every solve's merge has finished. The subgraphs'
+qubit-group classes run concurrently on the library's side streams
+(--serial-classes: in order), except in the steps that carry kernel events
+(the profiled warm-up step and the last tenth of the timed steps), which run
+them serially so that no other kernel overlaps the timed launches; the line
+also times both modes apart (solve.plain_classes).
 
 The same line carries the learned-warm-start solve of the same graph: the
 angle predictor (committed weights, trained on plain-method runs of other
@@ -165,9 +170,18 @@ def workload_solve(args, name):
     cfg = SolveConfig(p=3, iters=50, k=16, beam=4096)
     log(f"bench: graph {g}, {part.M} subgraphs of sizes {min(part.size)}..{max(part.size)}, p={cfg.p}, "
         f"iters={cfg.iters}, k={cfg.k}, W={cfg.beam}")
-    S = Solver(g, part, cfg, skip_edgeless=skip, gradient_memory=args.gradient_memory,
-               concurrent_classes=args.concurrent_classes)
+    conc = not args.serial_classes
+    S = Solver(g, part, cfg, skip_edgeless=skip, gradient_memory=args.gradient_memory, concurrent_classes=conc)
     from paper_2603_26232_amd import _abi
+
+    def classes(concurrent):
+        """Qubit-group classes on concurrent side streams or in serial order,
+        from the next batch build (every step starts with one) on."""
+        if concurrent:
+            S.batch.flags |= _abi.QAOA_FLAG_CONCURRENT_CLASSES
+        else:
+            S.batch.flags &= ~_abi.QAOA_FLAG_CONCURRENT_CLASSES
+
     ckpt = _abi.qaoa_gradient_checkpoints(S.batch.handle)
     nE = np.array([len(e[0]) for e in S.sub_edges])
     act = nE > 0
@@ -221,34 +235,33 @@ def workload_solve(args, name):
         return {"seconds": round(gs, 4), "eager_seconds": round(plain_s, 4), "speedup_vs_eager": round(plain_s / gs, 4),
                 "first_solve_with_capture_seconds": round(first, 3), "same_result_as_eager": r == ref}
 
-    def concurrent_compare(plain_s, ref):
-        """The same plain solves with the qubit-group classes on concurrent
-        side streams (the batch re-created with the flag, same workspace);
-        kernel timings overlap there, so the roofline stays serial."""
-        log(f"bench: plain solves with concurrent classes, {n_cmp} timed")
-        S.batch.flags |= _abi.QAOA_FLAG_CONCURRENT_CLASSES
+    def classes_compare():
+        """Plain solves with the classes concurrent, then in serial order (each
+        mode's first solve untimed); the results must be identical."""
+        log(f"bench: plain solves with concurrent and with serial classes, {n_cmp} timed each")
+        res = {}
         try:
-            step()
-            cs = time_solves(step, n_cmp)
-            r = result()
+            for mode in (True, False):
+                classes(mode)
+                step()
+                res[mode] = (time_solves(step, n_cmp), result())
         finally:
-            # the next solve's batch build drops the flag again
-            S.batch.flags &= ~_abi.QAOA_FLAG_CONCURRENT_CLASSES
-        log(f"bench: concurrent classes {cs:.4f} s/solve (serial {plain_s:.4f})")
-        return {"seconds": round(cs, 4), "serial_seconds": round(plain_s, 4),
-                "speedup_vs_serial": round(plain_s / cs, 4), "same_result_as_serial": r == ref}
+            classes(conc)
+        c, s_ = res[True][0], res[False][0]
+        log(f"bench: classes concurrent {c:.4f} s/solve, serial {s_:.4f} s/solve")
+        return {"concurrent_seconds": round(c, 4), "serial_seconds": round(s_, 4),
+                "concurrent_speedup": round(s_ / c, 4), "same_result": res[True][1] == res[False][1]}
 
     def extra(plain_s):
         """After the timed plain solves: their result, the plain solves with
-        the Adam loop replayed from a HIP graph and with concurrent classes,
-        the learned solves timed the same way, and the latency of one solve
-        of each kind."""
+        the Adam loop replayed from a HIP graph, with the classes concurrent
+        and serial, the learned solves timed the same way, and the latency of
+        one solve of each kind."""
         out = {"plain": dict(result(), seconds=round(plain_s, 4), adam_steps=cfg.iters, adam_lr=cfg.lr)}
         if not args.no_graph_compare:
             out["plain_graph_replay"] = graph_compare(plain_s, result())
-        if not args.concurrent_classes and not args.no_concurrent_compare:
-            ref = {k: out["plain"][k] for k in ("cut", "sum_E_with_edges")}
-            out["plain_concurrent_classes"] = concurrent_compare(plain_s, ref)
+        if not args.no_classes_compare:
+            out["plain_classes"] = classes_compare()
         if LS is None:
             return {"solve": out}
         log(f"bench: learned-warm-start solves ({args.warm_iters} Adam steps), {args.steps} timed")
@@ -312,7 +325,10 @@ def workload_solve(args, name):
                                "sample": f"every 4th subgraph of that sample ({len(one)}), {T1} Adam steps + "
                                          f"final evaluation"}}
 
-    config = {"workload": desc, "merge_overlaps_next_solve": overlap, "concurrent_classes": args.concurrent_classes,
+    config = {"workload": desc, "merge_overlaps_next_solve": overlap,
+              "classes": ("concurrent on side streams, serial in the last tenth of the timed steps (the steps "
+                          "that carry the dominant kernel's events) and in the profiled warm-up step") if conc
+              else "serial",
               "gradient_memory": ("forward checkpoints" if ckpt else "in place") + f" ({args.gradient_memory})",
               "vertices": g.num_vertices, "edges": g.num_edges,
               "subgraphs": part.M, "simulated_subgraphs": len(sim),
@@ -322,7 +338,7 @@ def workload_solve(args, name):
         config["learned_adam_steps"] = args.warm_iters
         config["predictor"] = os.path.basename(args.predictor)
     return dict(step=step, updates=(3 * cfg.iters + 1) * U, config=config, summary=summary, extra=extra,
-                cpu_baseline=cpu_baseline, close=S.close, dtype="fp32")
+                cpu_baseline=cpu_baseline, close=S.close, dtype="fp32", classes=classes, concurrent=conc)
 
 
 def workload_precision(args):
@@ -392,10 +408,11 @@ def main():
                     help="solve workloads: skip the plain solves with the Adam loop replayed from a HIP graph")
     ap.add_argument("--gradient-memory", choices=["auto", "checkpoints", "inplace"], default="auto",
                     help="forward checkpoints, one psi rebuilt in place, or the library's choice by size")
-    ap.add_argument("--concurrent-classes", action="store_true",
-                    help="run the qubit-group classes of the batch concurrently on side streams")
-    ap.add_argument("--no-concurrent-compare", action="store_true",
-                    help="solve workloads: skip the plain solves with concurrent classes")
+    ap.add_argument("--serial-classes", action="store_true",
+                    help="solve workloads: run the qubit-group classes in serial order throughout (default: "
+                         "concurrently on side streams, except in the profiled steps)")
+    ap.add_argument("--no-classes-compare", action="store_true",
+                    help="solve workloads: skip the plain solves timed with concurrent and with serial classes")
     ap.add_argument("--tuning", default="default",
                     help="group-split tuning table (JSON from paper_2603_26232_amd.autotune); 'default' = the "
                          "package's table if present, 'none' = untuned")
@@ -453,9 +470,16 @@ def main():
 
     # warm-up; the last warm-up step is timed kernel by kernel (every launch
     # bracketed by events) to find the kernel with the largest share
+    # with concurrent classes, the steps that carry kernel events (the
+    # profiled warm-up step, the last tenth of the timed steps) run the
+    # classes serially: overlapping launches would stretch each kernel's
+    # event-timed duration
+    classes = W.get("classes", lambda concurrent: None)
+    conc = W.get("concurrent", False)
     kern = {}
     for i in range(args.warmup):
         if i == args.warmup - 1:
+            classes(False)
             _abi.qaoa_profile_select(None)
             _abi.qaoa_profile_enable(1)
         step()
@@ -474,14 +498,17 @@ def main():
     nprof = max(1, args.steps // 10)
     _abi.qaoa_profile_select("-")
     _abi.qaoa_profile_enable(1)
+    classes(conc)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         if i == args.steps - nprof:
+            classes(False)
             _abi.qaoa_profile_select(dom)
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    classes(conc)
     timed = read_profile()
     _abi.qaoa_profile_enable(0)
     _abi.qaoa_profile_select(None)
@@ -503,7 +530,9 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "algo_bytes_per_launch": d["algo_bytes"] / d["launches"], "avg_launch_us": round(d["avg_us"], 2),
-                "traffic": (None if tr is None else tr["hbm_bytes_per_launch"])}
+                "traffic": (None if tr is None else tr["hbm_bytes_per_launch"]),
+                "measured_on": f"the last {nprof} of the {args.steps} timed steps" +
+                               (", qubit-group classes serial" if conc else "")}
     vr = valu_record(dom, args.workload) if args.mixer == "valu" else None
     if vr is not None:
         # the same kernel seen from the vector units: measured VALU issue rate
